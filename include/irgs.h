@@ -1,0 +1,218 @@
+/*
+ * irgs.h -- C ABI of the MI355X (gfx950) 2D Gaussian ray tracer.
+ *
+ * The library implements Trace(r_o, r_d) -> (c_rt, o_rt) of Sec. 3.2
+ * (Eq. 8) and its use as the visibility / indirect-radiance query
+ * (L_ind, 1 - V) <- Trace(x, w_i) of Sec. 3.3 (Eq. 14):
+ *   - a ray meets a surfel's plane at tau = n.(mu - r_o) / n.r_d   (Eq. 6);
+ *   - at p = r_o + tau r_d, u = (p-mu).t_u / s_u, v = (p-mu).t_v / s_v and
+ *     alpha = o exp(-(u^2+v^2)/2)                                   (Eq. 7);
+ *   - hits are collected by k-buffer marching (the k nearest after the last
+ *     composited hit, per round) in exact (tau, id) order and alpha-blended
+ *     front to back (Eq. 2), stopping once the transmittance T < T_min;
+ *   - the surfel frame (t_u, t_v, n) is the column set of the rotation of
+ *     the unit quaternion q = (w, x, y, z) (Sec. 3.1: quaternion + scaling
+ *     parameterisation; Sec. 3.2: two tangents and their cross product).
+ * A software LBVH over each surfel's support box stands in for the hardware
+ * BVH over icosahedron proxies of Eq. 5 (rebuilt or refit per iteration,
+ * Sec. 4 implementation details).
+ *
+ * Conventions for every entry point:
+ *   - pointers are DEVICE pointers unless stated otherwise; arrays are FP32
+ *     (or int32), row-major and contiguous;
+ *   - `stream` is a hipStream_t (NULL = the default stream); work is queued
+ *     asynchronously and no entry point synchronises the stream except
+ *     irgs_scene_build (it reads the tree depth back to the host);
+ *   - a return value < 0 is an error; nothing is thrown across the ABI;
+ *     irgs_last_error() returns a thread-local message about the last
+ *     failure on the calling thread.  Argument errors are reported before
+ *     any work is queued.  Kernel faults surface at the caller's next sync.
+ */
+#ifndef IRGS_H
+#define IRGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IRGS_OK = 0,
+    IRGS_E_INVALID = -1, /* bad argument: null required pointer, size, k, F */
+    IRGS_E_OOM = -2,     /* device allocation failed */
+    IRGS_E_HIP = -3,     /* a HIP call or kernel launch failed */
+    IRGS_E_STATE = -4,   /* scene not built, or built with other alpha_min/sigma */
+    IRGS_E_BUSY = -5     /* reserved */
+} irgs_status;
+
+typedef struct irgs_scene_s* irgs_scene; /* opaque, owned by the library */
+
+/* Surfel parameters, BORROWED by a scene (the caller keeps them alive):
+ *   mu (N x 3) centres; quat (N x 4) raw quaternions (w,x,y,z), normalised
+ *   inside; scale (N x 2) activated scales (s_u, s_v) > 0; opacity (N)
+ *   activated opacity in [0,1]; feat (N x F) per-surfel features blended
+ *   along the ray (RGB, albedo, roughness, ...).  A surfel with a non-finite
+ *   value, a zero quaternion or a non-positive scale is never hit. */
+typedef struct {
+    const float* mu;
+    const float* quat;
+    const float* scale;
+    const float* opacity;
+    const float* feat;
+} irgs_surfels;
+
+/* Trace parameters.
+ *   k             k-buffer size, one of 1, 2, 4, 8, 16, 32, 64 (results do
+ *                 not depend on k; it only changes the work per round)
+ *   feature_dim   F, must equal the scene's F (1..64)
+ *   alpha_min     minimum alpha of a hit (the alpha_min of Eq. 5)
+ *   T_min         stop once the transmittance falls below this
+ *   t_min, t_max  hits need t_min < tau < t_max
+ *   support_sigma hits need u^2 + v^2 <= support_sigma^2
+ *   flags         IRGS_FLAG_* below
+ * alpha_min and support_sigma are fixed at build time (they size the boxes);
+ * tracing with other values returns IRGS_E_STATE. */
+typedef struct {
+    int32_t k;
+    int32_t feature_dim;
+    float alpha_min;
+    float T_min;
+    float t_min;
+    float t_max;
+    float support_sigma;
+    uint32_t flags;
+} irgs_params;
+
+#define IRGS_FLAG_BRUTE_FORCE 1u /* trace: test every surfel, no BVH */
+#define IRGS_FLAG_RECOMPUTE 2u   /* backward: re-march instead of reading saved hits */
+
+/* Outputs of a trace, caller-allocated (R = number of rays):
+ *   opacity (R)      accumulated opacity O = sum T_i alpha_i (o_rt of Eq. 8;
+ *                    visibility V = 1 - O, Eq. 14)
+ *   feat (R x F)     blended features sum T_i alpha_i f_i (c_rt / L_ind)
+ *   depth (R)        UNnormalised depth sum T_i alpha_i tau_i (normalised
+ *                    depth of Eq. 9 is depth / opacity)
+ *   T (R)            final transmittance, optional (NULL)
+ *   n_hits (R)       number of composited hits, optional; required by
+ *                    irgs_trace_backward
+ *   hit_ids (R x H_cap)  ids of the first H_cap composited hits in order,
+ *                    optional; entries past n_hits are left untouched
+ *   hit_T (R x H_cap)    transmittance before each of those hits, optional
+ *                    (needs hit_ids)
+ * A ray with a non-finite component or a zero direction gets O = 0, F = 0,
+ * D = 0, T = 1, n_hits = 0. */
+typedef struct {
+    float* opacity;
+    float* feat;
+    float* depth;
+    float* T;
+    int32_t* n_hits;
+    int32_t* hit_ids;
+    float* hit_T;
+    int32_t H_cap;
+} irgs_out;
+
+/* Upstream gradients dL/dO (R), dL/dF (R x F), dL/dD (R); any may be NULL
+ * (treated as zero).  Rays whose upstream gradients are all zero are
+ * skipped. */
+typedef struct {
+    const float* g_opacity;
+    const float* g_feat;
+    const float* g_depth;
+} irgs_grad_in;
+
+/* Gradient outputs, ACCUMULATED (+=) so the caller zeroes them; any may be
+ * NULL to skip it.  Shapes as irgs_surfels; quat is the gradient with
+ * respect to the raw (unnormalised) quaternion. */
+typedef struct {
+    float* mu;
+    float* quat;
+    float* scale;
+    float* opacity;
+    float* feat;
+} irgs_grads;
+
+/* One work item of a packed launch: rays [ray_begin, ray_begin+ray_count)
+ * of ro/rd (R x 3 each), traced against scenes[scene]; outputs are written
+ * at the same ray indices of `out` (its feat has the scene's F columns). */
+typedef struct {
+    int32_t scene;
+    int32_t pad;
+    int64_t ray_begin;
+    int64_t ray_count;
+    const float* ro;
+    const float* rd;
+    irgs_out out;
+} irgs_work;
+
+/* Bytes the library allocates for a scene of n surfels (records, nodes,
+ * build scratch), and the per-call scratch of a trace of R rays. */
+size_t irgs_scene_bytes(int64_t n, int32_t F);
+size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags);
+
+/* Create a scene over borrowed parameters (no device work, no allocation
+ * beyond the handle).  n >= 0, 1 <= F <= 64. */
+irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, irgs_scene* out);
+
+/* Point the scene at other parameter buffers of the same shape (the tree
+ * must be refit or rebuilt before the next trace). */
+irgs_status irgs_scene_set_params(irgs_scene scene, const irgs_surfels* params);
+
+/* Build: per-surfel records and support boxes, Morton codes, radix sort,
+ * hierarchy, bottom-up boxes.  Allocates the scene's device buffers on
+ * first use.  Uses params->alpha_min and params->support_sigma.  Reads the
+ * tree depth back (synchronises `stream`). */
+irgs_status irgs_scene_build(irgs_scene scene, const irgs_params* params, void* stream);
+
+/* Refit after the parameters changed in place: records, leaf boxes and
+ * internal boxes recomputed, tree topology kept.  Asynchronous. */
+irgs_status irgs_scene_refit(irgs_scene scene, void* stream);
+
+/* Forward trace of R rays, ro and rd (R x 3, directions need not be unit:
+ * tau is measured in units of r_d).  Uses the BVH unless
+ * IRGS_FLAG_BRUTE_FORCE is set (then the scene must still be built, for the
+ * records). */
+irgs_status irgs_trace(irgs_scene scene, const irgs_params* params, int64_t R, const float* ro, const float* rd,
+                       const irgs_out* out, void* stream);
+
+/* Backward of irgs_trace over the same rays: accumulates parameter
+ * gradients.  `saved` is the irgs_out of the forward call: n_hits is
+ * required; with hit_ids and hit_T present (and IRGS_FLAG_RECOMPUTE unset)
+ * rays with n_hits <= H_cap replay their saved hits, every other ray
+ * re-marches its hits.  Parameters must not have changed since the forward
+ * trace. */
+irgs_status irgs_trace_backward(irgs_scene scene, const irgs_params* params, int64_t R, const float* ro,
+                                const float* rd, const irgs_out* saved, const irgs_grad_in* grad_in,
+                                irgs_grads* grads, void* stream);
+
+/* One persistent launch over the work items of several built scenes
+ * (`items` is a HOST array, copied by the call).  Every scene must share
+ * alpha_min/support_sigma with `params`; params->feature_dim must be >= the
+ * largest F.  k must be 16 or 32. */
+irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const irgs_params* params,
+                              const irgs_work* items, int32_t n_items, void* stream);
+
+/* Tree statistics of a built scene (host outputs, any may be NULL):
+ * number of internal nodes, maximum leaf depth. */
+irgs_status irgs_scene_info(irgs_scene scene, int64_t* n_internal, int32_t* max_depth);
+
+/* Copy the tree of a built scene into caller DEVICE buffers (any NULL is
+ * skipped): order (N, int32: Morton position -> surfel id), nodes
+ * ((N-1) x 16 int32 words: 12 box floats as bits, child0, child1, parent,
+ * 0), leaf_parent (N).  For structural tests. */
+irgs_status irgs_scene_export(irgs_scene scene, int32_t* order, int32_t* nodes, int32_t* leaf_parent,
+                              void* stream);
+
+irgs_status irgs_scene_destroy(irgs_scene scene);
+
+const char* irgs_status_str(irgs_status status);
+const char* irgs_last_error(void);
+const char* irgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRGS_H */

@@ -99,10 +99,12 @@ def loss_and_hits(surfels, ro, rd, gO, gF, gD, hit_cap, **kw):
     return L, r
 
 
-def fd_grad(surfels, ro, rd, gO, gF, gD, which=None, rel_h: float = 1e-6, hit_cap: int = 512, **kw):
+def fd_grad(surfels, ro, rd, gO, gF, gD, which=None, rel_h: float = 1e-6, hit_cap: int = 512,
+            surfel_idx=None, **kw):
     """Central finite differences of L.  Returns (grads, skipped) where grads
-    is a dict of arrays (NaN where skipped) and skipped counts the parameters
-    whose +-h perturbation changed some ray's ordered hit list."""
+    is a dict of arrays (NaN where skipped or not requested) and skipped
+    counts the parameters whose +-h perturbation changed some ray's ordered
+    hit list.  `surfel_idx` restricts the perturbed surfels."""
     base = [np.array(a, dtype=np.float64, copy=True) for a in surfels]
     _, ref = loss_and_hits(base, ro, rd, gO, gF, gD, hit_cap, **kw)
     ref_hits, ref_n = ref["hits"], ref["n_hits"]
@@ -116,7 +118,9 @@ def fd_grad(surfels, ro, rd, gO, gF, gD, which=None, rel_h: float = 1e-6, hit_ca
         g = np.full(arr.shape, np.nan)
         flat = arr.reshape(-1)
         gflat = g.reshape(-1)
-        for j in range(flat.size):
+        per = flat.size // max(arr.shape[0], 1)
+        rows = range(arr.shape[0]) if surfel_idx is None else surfel_idx
+        for j in (int(r) * per + c for r in rows for c in range(per)):
             x0 = flat[j]
             h = rel_h * (abs(x0) if name == "scale" else max(1.0, abs(x0)))
             vals = []

@@ -1,0 +1,460 @@
+// C ABI of the 2D Gaussian ray tracer: argument checks, device buffers of a
+// scene, per-call scratch, and dispatch to the kernels.  Declared in
+// include/irgs.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/irgs.h"
+#include "irgs_internal.hpp"
+
+using namespace irgs;
+
+struct irgs_scene_s {
+    int64_t n = 0;
+    int32_t F = 0;
+    irgs_surfels p{};
+    bool built = false;
+    float alpha_min = 0.0f;
+    float sigma = 0.0f;
+    int32_t max_depth = 0;
+    SurfelRec* rec = nullptr;
+    BvhNode* nodes = nullptr;
+    int* leaf_parent = nullptr;
+    uint32_t* order = nullptr;
+    float* leafbox = nullptr;
+    uint32_t* counters = nullptr;
+    int* depth = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+irgs_status fail(irgs_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+irgs_status fail(irgs_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+irgs_status hip_fail(hipError_t e, const char* what)
+{
+    if (e == hipErrorOutOfMemory) return fail(IRGS_E_OOM, "%s: out of device memory", what);
+    return fail(IRGS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t n_internal(int64_t n) { return n > 1 ? n - 1 : 1; }
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count)
+{
+    return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count > 0 ? count : 1));
+}
+
+void free_scene_buffers(irgs_scene s)
+{
+    hipFree(s->rec);
+    hipFree(s->nodes);
+    hipFree(s->leaf_parent);
+    hipFree(s->order);
+    hipFree(s->leafbox);
+    hipFree(s->counters);
+    hipFree(s->depth);
+    s->rec = nullptr;
+    s->nodes = nullptr;
+    s->leaf_parent = nullptr;
+    s->order = nullptr;
+    s->leafbox = nullptr;
+    s->counters = nullptr;
+    s->depth = nullptr;
+    s->built = false;
+}
+
+irgs_status check_params(const irgs_params* p, int32_t F)
+{
+    if (!p) return fail(IRGS_E_INVALID, "params is NULL");
+    const int k = p->k;
+    if (!(k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64))
+        return fail(IRGS_E_INVALID, "k = %d: must be one of 1, 2, 4, 8, 16, 32, 64", k);
+    if (p->feature_dim != F) return fail(IRGS_E_INVALID, "feature_dim %d != scene F %d", p->feature_dim, F);
+    if (!(p->alpha_min >= 0.0f) || !(p->T_min >= 0.0f) || std::isnan(p->t_min) || std::isnan(p->t_max) ||
+        !(p->support_sigma > 0.0f))
+        return fail(IRGS_E_INVALID, "alpha_min, T_min >= 0, support_sigma > 0 and finite-or-inf t window required");
+    return IRGS_OK;
+}
+
+BuildArgs build_args(irgs_scene s)
+{
+    BuildArgs a{};
+    a.n = static_cast<int>(s->n);
+    a.mu = s->p.mu;
+    a.quat = s->p.quat;
+    a.scale = s->p.scale;
+    a.opac = s->p.opacity;
+    a.alpha_min = s->alpha_min;
+    a.sigma = s->sigma;
+    a.order = s->order;
+    a.sorted_keys = nullptr;
+    a.rec = s->rec;
+    a.leafbox = s->leafbox;
+    a.nodes = s->nodes;
+    a.leaf_parent = s->leaf_parent;
+    a.counters = s->counters;
+    a.depth = s->depth;
+    return a;
+}
+
+SceneView view_of(irgs_scene s)
+{
+    SceneView v{};
+    v.rec = s->rec;
+    v.nodes = s->nodes;
+    v.feat = s->p.feat;
+    v.n = static_cast<int32_t>(s->n);
+    v.F = s->F;
+    return v;
+}
+
+int ovf_slots_of(irgs_scene s)
+{
+    const int extra = s->max_depth - kStackLds + 1;
+    return extra > 0 ? extra : 0;
+}
+
+OutPtrs out_ptrs(const irgs_out* o)
+{
+    OutPtrs r{};
+    r.O = o->opacity;
+    r.feat = o->feat;
+    r.D = o->depth;
+    r.T = o->T;
+    r.n_hits = o->n_hits;
+    r.hit_ids = o->hit_ids;
+    r.hit_T = o->hit_ids ? o->hit_T : nullptr;
+    r.H_cap = o->hit_ids ? o->H_cap : 0;
+    return r;
+}
+
+irgs_status check_trace_common(irgs_scene s, const irgs_params* p, int64_t R, const float* ro, const float* rd)
+{
+    if (!s) return fail(IRGS_E_INVALID, "scene is NULL");
+    irgs_status st = check_params(p, s->F);
+    if (st != IRGS_OK) return st;
+    if (R < 0) return fail(IRGS_E_INVALID, "R = %lld < 0", static_cast<long long>(R));
+    if (R > 0 && (!ro || !rd)) return fail(IRGS_E_INVALID, "ro/rd is NULL");
+    if (!s->built) return fail(IRGS_E_STATE, "scene is not built");
+    if (p->alpha_min != s->alpha_min || p->support_sigma != s->sigma)
+        return fail(IRGS_E_STATE, "scene was built with alpha_min %g, support_sigma %g (got %g, %g)",
+                    static_cast<double>(s->alpha_min), static_cast<double>(s->sigma),
+                    static_cast<double>(p->alpha_min), static_cast<double>(p->support_sigma));
+    if (s->n > 0 && !s->p.feat) return fail(IRGS_E_INVALID, "scene features are NULL");
+    return IRGS_OK;
+}
+
+TraceParams trace_params(const irgs_params* p, int32_t F)
+{
+    TraceParams t{};
+    t.t_min = p->t_min;
+    t.t_max = p->t_max;
+    t.T_min = p->T_min;
+    t.F = F;
+    return t;
+}
+
+struct AsyncBuf {
+    void* p = nullptr;
+    hipStream_t st = nullptr;
+    ~AsyncBuf()
+    {
+        if (p) hipFreeAsync(p, st);
+    }
+    hipError_t alloc(size_t bytes, hipStream_t s)
+    {
+        st = s;
+        if (bytes == 0) return hipSuccess;
+        return hipMallocAsync(&p, bytes, s);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* irgs_version(void) { return "irgs-gfx950 0.1"; }
+
+const char* irgs_last_error(void) { return g_err.c_str(); }
+
+const char* irgs_status_str(irgs_status s)
+{
+    switch (s) {
+        case IRGS_OK: return "ok";
+        case IRGS_E_INVALID: return "invalid argument";
+        case IRGS_E_OOM: return "out of device memory";
+        case IRGS_E_HIP: return "HIP error";
+        case IRGS_E_STATE: return "invalid scene state";
+        case IRGS_E_BUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+size_t irgs_scene_bytes(int64_t n, int32_t F)
+{
+    (void)F;
+    if (n < 0) return 0;
+    size_t sort = 0;
+    lbvh_sort_scratch_bytes(static_cast<int>(n), &sort);
+    const size_t ni = static_cast<size_t>(n_internal(n));
+    return static_cast<size_t>(n) * (sizeof(SurfelRec) + sizeof(int) + sizeof(uint32_t) + 6 * sizeof(float)) +
+           ni * (sizeof(BvhNode) + sizeof(uint32_t)) + sizeof(int) + sort;
+}
+
+size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
+{
+    (void)F;
+    if (R <= 0) return 0;
+    const size_t thr = static_cast<size_t>(trace_threads(R));
+    size_t b = thr * 64 * sizeof(int);  // worst-case stack overflow area
+    if (flags & IRGS_FLAG_RECOMPUTE) b += thr * kBwdCheckpoints * 4 * sizeof(float);
+    return b;
+}
+
+irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, irgs_scene* out)
+{
+    if (!out) return fail(IRGS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || n > (int64_t(1) << 30)) return fail(IRGS_E_INVALID, "n = %lld out of range", (long long)n);
+    if (F < 1 || F > kMaxF) return fail(IRGS_E_INVALID, "F = %d out of range [1, %d]", F, kMaxF);
+    if (!params) return fail(IRGS_E_INVALID, "params is NULL");
+    if (n > 0 && (!params->mu || !params->quat || !params->scale || !params->opacity || !params->feat))
+        return fail(IRGS_E_INVALID, "a surfel parameter pointer is NULL");
+    irgs_scene s = new (std::nothrow) irgs_scene_s();
+    if (!s) return fail(IRGS_E_OOM, "host allocation failed");
+    s->n = n;
+    s->F = F;
+    s->p = *params;
+    *out = s;
+    return IRGS_OK;
+}
+
+irgs_status irgs_scene_set_params(irgs_scene s, const irgs_surfels* params)
+{
+    if (!s || !params) return fail(IRGS_E_INVALID, "scene or params is NULL");
+    if (s->n > 0 && (!params->mu || !params->quat || !params->scale || !params->opacity || !params->feat))
+        return fail(IRGS_E_INVALID, "a surfel parameter pointer is NULL");
+    s->p = *params;
+    return IRGS_OK;
+}
+
+irgs_status irgs_scene_build(irgs_scene s, const irgs_params* p, void* stream)
+{
+    if (!s) return fail(IRGS_E_INVALID, "scene is NULL");
+    if (!p) return fail(IRGS_E_INVALID, "params is NULL");
+    if (!(p->alpha_min >= 0.0f) || !(p->support_sigma > 0.0f))
+        return fail(IRGS_E_INVALID, "alpha_min >= 0 and support_sigma > 0 required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = s->n;
+    hipError_t e = hipSuccess;
+    if (!s->rec) {
+        if ((e = dalloc(&s->rec, n)) != hipSuccess || (e = dalloc(&s->nodes, n_internal(n))) != hipSuccess ||
+            (e = dalloc(&s->leaf_parent, n)) != hipSuccess || (e = dalloc(&s->order, n)) != hipSuccess ||
+            (e = dalloc(&s->leafbox, 6 * n)) != hipSuccess || (e = dalloc(&s->counters, n_internal(n))) != hipSuccess ||
+            (e = dalloc(&s->depth, 1)) != hipSuccess) {
+            free_scene_buffers(s);
+            return hip_fail(e, "scene allocation");
+        }
+    }
+    s->alpha_min = p->alpha_min;
+    s->sigma = p->support_sigma;
+    s->built = false;
+    if (n == 0) {
+        s->max_depth = 0;
+        s->built = true;
+        return IRGS_OK;
+    }
+    size_t sort_bytes = 0;
+    lbvh_sort_scratch_bytes(static_cast<int>(n), &sort_bytes);
+    void* scratch = nullptr;
+    if ((e = hipMalloc(&scratch, sort_bytes)) != hipSuccess) return hip_fail(e, "build scratch");
+    e = lbvh_build(build_args(s), scratch, st);
+    int depth = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&depth, s->depth, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(scratch);
+    if (e != hipSuccess) return hip_fail(e, "build");
+    s->max_depth = depth;
+    s->built = true;
+    return IRGS_OK;
+}
+
+irgs_status irgs_scene_refit(irgs_scene s, void* stream)
+{
+    if (!s) return fail(IRGS_E_INVALID, "scene is NULL");
+    if (!s->built) return fail(IRGS_E_STATE, "scene is not built");
+    hipError_t e = lbvh_refit(build_args(s), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "refit");
+    return IRGS_OK;
+}
+
+irgs_status irgs_trace(irgs_scene s, const irgs_params* p, int64_t R, const float* ro, const float* rd,
+                       const irgs_out* out, void* stream)
+{
+    irgs_status st = check_trace_common(s, p, R, ro, rd);
+    if (st != IRGS_OK) return st;
+    if (!out) return fail(IRGS_E_INVALID, "out is NULL");
+    if (R > 0 && (!out->opacity || !out->feat || !out->depth))
+        return fail(IRGS_E_INVALID, "out->opacity, feat and depth are required");
+    if (out->hit_ids && out->H_cap < 0) return fail(IRGS_E_INVALID, "H_cap < 0");
+    if (R == 0) return IRGS_OK;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const bool bvh = !(p->flags & IRGS_FLAG_BRUTE_FORCE);
+    const int slots = bvh ? ovf_slots_of(s) : 0;
+    AsyncBuf ovf;
+    hipError_t e = ovf.alloc(static_cast<size_t>(trace_threads(R)) * slots * sizeof(int), hs);
+    if (e != hipSuccess) return hip_fail(e, "trace scratch");
+    e = launch_trace(view_of(s), trace_params(p, s->F), p->k, bvh, R, ro, rd, out_ptrs(out),
+                     static_cast<int*>(ovf.p), slots, hs);
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return IRGS_OK;
+}
+
+irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, const float* ro, const float* rd,
+                                const irgs_out* saved, const irgs_grad_in* gin, irgs_grads* grads, void* stream)
+{
+    irgs_status st = check_trace_common(s, p, R, ro, rd);
+    if (st != IRGS_OK) return st;
+    if (!saved || !gin || !grads) return fail(IRGS_E_INVALID, "saved, grad_in and grads are required");
+    if (R > 0 && !saved->n_hits) return fail(IRGS_E_INVALID, "saved->n_hits is required");
+    if (R == 0 || s->n == 0) return IRGS_OK;
+    const bool use_saved = !(p->flags & IRGS_FLAG_RECOMPUTE) && saved->hit_ids && saved->hit_T && saved->H_cap > 0;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int slots = ovf_slots_of(s);
+    const size_t thr = static_cast<size_t>(trace_threads(R));
+    AsyncBuf ovf, ck;
+    hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
+    if (e == hipSuccess) e = ck.alloc(thr * kBwdCheckpoints * 4 * sizeof(float), hs);
+    if (e != hipSuccess) return hip_fail(e, "backward scratch");
+    RawSurfels raw{s->p.mu, s->p.quat, s->p.scale, s->p.opacity, s->p.feat};
+    GradIn g{gin->g_opacity, gin->g_feat, gin->g_depth};
+    GradOut go{grads->mu, grads->quat, grads->scale, grads->opacity, grads->feat};
+    OutPtrs sv = out_ptrs(saved);
+    e = launch_backward(view_of(s), raw, trace_params(p, s->F), p->k, R, ro, rd, sv, use_saved, g, go,
+                        static_cast<int*>(ovf.p), slots, static_cast<float*>(ck.p), hs);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return IRGS_OK;
+}
+
+irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const irgs_params* p,
+                              const irgs_work* items, int32_t n_items, void* stream)
+{
+    if (!scenes || n_scenes <= 0) return fail(IRGS_E_INVALID, "no scenes");
+    if (!p) return fail(IRGS_E_INVALID, "params is NULL");
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(IRGS_E_INVALID, "bad items");
+    if (p->k != 16 && p->k != 32) return fail(IRGS_E_INVALID, "packed launch supports k = 16 or 32");
+    int32_t Fmax = 0;
+    int slots = 0;
+    std::vector<SceneView> views(n_scenes);
+    for (int i = 0; i < n_scenes; ++i) {
+        irgs_scene s = scenes[i];
+        if (!s) return fail(IRGS_E_INVALID, "scene %d is NULL", i);
+        if (!s->built) return fail(IRGS_E_STATE, "scene %d is not built", i);
+        if (p->alpha_min != s->alpha_min || p->support_sigma != s->sigma)
+            return fail(IRGS_E_STATE, "scene %d was built with other alpha_min/support_sigma", i);
+        if (s->n > 0 && !s->p.feat) return fail(IRGS_E_INVALID, "scene %d features are NULL", i);
+        Fmax = s->F > Fmax ? s->F : Fmax;
+        slots = ovf_slots_of(s) > slots ? ovf_slots_of(s) : slots;
+        views[i] = view_of(s);
+    }
+    if (p->feature_dim < Fmax) return fail(IRGS_E_INVALID, "feature_dim %d < largest scene F %d", p->feature_dim, Fmax);
+    std::vector<WorkItem> w(n_items);
+    int64_t chunks = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const irgs_work& it = items[i];
+        if (it.scene < 0 || it.scene >= n_scenes) return fail(IRGS_E_INVALID, "item %d: bad scene %d", i, it.scene);
+        if (it.ray_begin < 0 || it.ray_count < 0) return fail(IRGS_E_INVALID, "item %d: negative range", i);
+        if (it.ray_count > 0 && (!it.ro || !it.rd || !it.out.opacity || !it.out.feat || !it.out.depth))
+            return fail(IRGS_E_INVALID, "item %d: NULL ray or output pointer", i);
+        if (it.out.hit_ids && it.out.H_cap < 0) return fail(IRGS_E_INVALID, "item %d: H_cap < 0", i);
+        w[i].scene = it.scene;
+        w[i].ray_begin = it.ray_begin;
+        w[i].ray_count = it.ray_count;
+        w[i].chunk_begin = chunks;
+        w[i].ro = it.ro;
+        w[i].rd = it.rd;
+        w[i].out = out_ptrs(&it.out);
+        chunks += (it.ray_count + kBlock - 1) / kBlock;
+    }
+    if (chunks == 0) return IRGS_OK;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int grid = static_cast<int>(chunks < 2048 ? chunks : 2048);
+    const size_t thr = static_cast<size_t>(grid) * kBlock;
+    const size_t vb = sizeof(SceneView) * n_scenes, wb = sizeof(WorkItem) * n_items;
+    const size_t items_off = (vb + 63) / 64 * 64;
+    const size_t counter_off = (items_off + wb + 63) / 64 * 64;
+    AsyncBuf meta, ovf;
+    hipError_t e = meta.alloc(counter_off + 64, hs);
+    if (e == hipSuccess) e = ovf.alloc(thr * slots * sizeof(int), hs);
+    if (e != hipSuccess) return hip_fail(e, "packed scratch");
+    char* base = static_cast<char*>(meta.p);
+    SceneView* dviews = reinterpret_cast<SceneView*>(base);
+    WorkItem* ditems = reinterpret_cast<WorkItem*>(base + items_off);
+    int* counter = reinterpret_cast<int*>(base + counter_off);
+    // Pageable host sources: the copies are staged before hipMemcpyAsync
+    // returns, so the vectors may go out of scope afterwards.
+    e = hipMemcpyAsync(dviews, views.data(), vb, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(ditems, w.data(), wb, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = fill_u32(counter, 1, 0u, hs);
+    if (e == hipSuccess) {
+        TraceParams tp = trace_params(p, Fmax);
+        e = launch_packed(dviews, ditems, n_items, chunks, tp, p->k, static_cast<int*>(ovf.p), slots, counter, grid,
+                          hs);
+    }
+    if (e != hipSuccess) return hip_fail(e, "packed launch");
+    return IRGS_OK;
+}
+
+irgs_status irgs_scene_info(irgs_scene s, int64_t* n_int, int32_t* max_depth)
+{
+    if (!s) return fail(IRGS_E_INVALID, "scene is NULL");
+    if (!s->built) return fail(IRGS_E_STATE, "scene is not built");
+    if (n_int) *n_int = s->n > 1 ? s->n - 1 : (s->n == 1 ? 1 : 0);
+    if (max_depth) *max_depth = s->max_depth;
+    return IRGS_OK;
+}
+
+irgs_status irgs_scene_export(irgs_scene s, int32_t* order, int32_t* nodes, int32_t* leaf_parent, void* stream)
+{
+    if (!s) return fail(IRGS_E_INVALID, "scene is NULL");
+    if (!s->built) return fail(IRGS_E_STATE, "scene is not built");
+    if (s->n == 0) return IRGS_OK;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (order) e = hipMemcpyAsync(order, s->order, sizeof(int32_t) * s->n, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess && nodes)
+        e = hipMemcpyAsync(nodes, s->nodes, sizeof(BvhNode) * n_internal(s->n), hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess && leaf_parent)
+        e = hipMemcpyAsync(leaf_parent, s->leaf_parent, sizeof(int32_t) * s->n, hipMemcpyDeviceToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "export");
+    return IRGS_OK;
+}
+
+irgs_status irgs_scene_destroy(irgs_scene s)
+{
+    if (!s) return IRGS_OK;
+    free_scene_buffers(s);  // hipFree waits for work still using the buffers
+    delete s;
+    return IRGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Device-side building blocks of the 2D Gaussian ray tracer (gfx950).
+//
+// Geometry follows Sec. 3.2 of the paper:
+//   * a surfel has centre mu, opacity o, a rotation quaternion q = (w,x,y,z)
+//     whose rotation matrix has columns (t_u, t_v, n), and scales (s_u, s_v);
+//   * Eq. 6: the ray meets the surfel plane at tau = n.(mu - r_o) / n.r_d;
+//   * Eq. 7: at p = r_o + tau r_d the local coordinates are
+//     u = (p - mu).t_u / s_u and v = (p - mu).t_v / s_v and the influence is
+//     G = exp(-(u^2 + v^2) / 2); alpha = o G;
+//   * Eq. 2 / Eq. 8: hits are alpha-blended front to back.
+// Readings fixed here (the paper gives no value): a hit needs
+// t_min < tau < t_max, u^2 + v^2 <= min(sigma^2, 2 ln(o / alpha_min)) (the
+// support cap and the alpha_min test of Eq. 5's proxy, both inclusive);
+// hits are ordered by (tau, surfel id); compositing includes a hit and then
+// stops once T < T_min.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace irgs {
+
+constexpr int kBlock = 256;          // threads per block of the trace kernels
+constexpr int kStackLds = 24;        // per-lane traversal stack entries kept in LDS
+constexpr int kLeafBit = 0x80000000; // child reference: leaf flag
+constexpr int kNoChild = -1;         // child reference: empty slot (N == 1 root)
+
+// 64-byte surfel record, stored in Morton (BVH leaf) order.
+//   a = (mu.xyz, o)            b = (n.xyz, rho2_max)
+//   c = (t_u / s_u, id bits)   d = (t_v / s_v, 0)
+// rho2_max = min(sigma^2, 2 ln(o / alpha_min)), or -1 for a surfel that can
+// never be hit (o < alpha_min or an invalid parameter).
+struct __align__(16) SurfelRec {
+    float4 a, b, c, d;
+};
+
+// Internal BVH node: the boxes of both children plus their references.
+// A reference r >= 0 is an internal node, r with kLeafBit set is the leaf at
+// Morton position (r & ~kLeafBit), kNoChild is an empty slot.
+struct __align__(16) BvhNode {
+    float4 p0;  // lo0.xyz, hi0.x
+    float4 p1;  // hi0.yz, lo1.xy
+    float4 p2;  // lo1.z, hi1.xyz
+    int4 ch;    // child0, child1, parent, unused
+};
+
+struct Box {
+    float lo[3], hi[3];
+};
+
+// What a trace kernel needs of one scene (passed by value).
+struct SceneView {
+    const SurfelRec* rec;  // N records, Morton order
+    const BvhNode* nodes;  // N-1 internal nodes (N == 1: one node), root = 0
+    const float* feat;     // N x F, caller layout (original ids)
+    int32_t n;
+    int32_t F;
+    int32_t root_is_leaf;  // unused (kept for layout), root always node 0
+    int32_t pad;
+};
+
+struct TraceParams {
+    float t_min, t_max, T_min;
+    int32_t F;
+};
+
+struct Ray {
+    float ox, oy, oz, dx, dy, dz;
+};
+
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz)
+{
+    return fmaf(ax, bx, fmaf(ay, by, az * bz));
+}
+
+// Columns (t_u, t_v, n) of the rotation of q = (w,x,y,z), normalised here.
+// Returns the norm of q.
+__device__ __forceinline__ float quat_frame(float4 q, float* tu, float* tv, float* nn)
+{
+    float qn = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+    float inv = 1.0f / qn;
+    float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
+    tu[0] = 1.0f - 2.0f * (y * y + z * z);
+    tu[1] = 2.0f * (x * y + w * z);
+    tu[2] = 2.0f * (x * z - w * y);
+    tv[0] = 2.0f * (x * y - w * z);
+    tv[1] = 1.0f - 2.0f * (x * x + z * z);
+    tv[2] = 2.0f * (y * z + w * x);
+    nn[0] = 2.0f * (x * z + w * y);
+    nn[1] = 2.0f * (y * z - w * x);
+    nn[2] = 1.0f - 2.0f * (x * x + y * y);
+    return qn;
+}
+
+// Eq. 6-7 against one record.  Returns true for a hit strictly after the
+// resume key (t_last, id_last) and inside (t_min, t_max); writes tau and
+// rho2 = u^2 + v^2.  Every kernel (brute force, BVH, packed, backward
+// recompute) calls this same function, so a given (ray, surfel) pair is
+// decided and ordered identically everywhere.
+__device__ __forceinline__ bool hit_test(const SurfelRec& s, const Ray& r, float t_min, float t_max,
+                                         float* tau_out, float* rho2_out)
+{
+    const float wx = s.a.x - r.ox, wy = s.a.y - r.oy, wz = s.a.z - r.oz;
+    const float den = dot3(s.b.x, s.b.y, s.b.z, r.dx, r.dy, r.dz);
+    const float num = dot3(s.b.x, s.b.y, s.b.z, wx, wy, wz);
+    const float tau = num / den;
+    // den == 0 gives +-inf or NaN, both rejected by the window test.
+    if (!(tau > t_min && tau < t_max)) return false;
+    const float px = fmaf(tau, r.dx, -wx), py = fmaf(tau, r.dy, -wy), pz = fmaf(tau, r.dz, -wz);
+    const float u = dot3(px, py, pz, s.c.x, s.c.y, s.c.z);
+    const float v = dot3(px, py, pz, s.d.x, s.d.y, s.d.z);
+    const float rho2 = fmaf(u, u, v * v);
+    if (!(rho2 <= s.b.w)) return false;
+    *tau_out = tau;
+    *rho2_out = rho2;
+    return true;
+}
+
+__device__ __forceinline__ SurfelRec load_rec(const SurfelRec* __restrict__ rec, int i)
+{
+    const float4* p = reinterpret_cast<const float4*>(rec + i);
+    SurfelRec s;
+    s.a = p[0];
+    s.b = p[1];
+    s.c = p[2];
+    s.d = p[3];
+    return s;
+}
+
+// Strict lexicographic order on (tau, id).
+__device__ __forceinline__ bool key_less(float ta, int ia, float tb, int ib)
+{
+    return ta < tb || (ta == tb && ia < ib);
+}
+
+// Slab test of a ray against a box, returning the entry distance; the box is
+// accepted when it overlaps [lo, hi] along the ray.  `hi` must be finite.
+// An empty box is stored with every coordinate = +inf, which this test
+// always rejects (the +inf slab of an axis with positive inverse direction
+// pushes the entry to +inf, and with all inverse directions negative the
+// exit drops to -inf).
+__device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, float hy, float hz,
+                                        float ox, float oy, float oz, float ix, float iy, float iz, float lo,
+                                        float hi, float* t_enter)
+{
+    float t0x = (lx - ox) * ix, t1x = (hx - ox) * ix;
+    float t0y = (ly - oy) * iy, t1y = (hy - oy) * iy;
+    float t0z = (lz - oz) * iz, t1z = (hz - oz) * iz;
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), lo));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), hi));
+    *t_enter = tn;
+    return tn <= tf;
+}
+
+__device__ __forceinline__ float safe_inv(float d)
+{
+    const float tiny = 1e-20f;
+    float dd = fabsf(d) < tiny ? copysignf(tiny, d) : d;
+    return 1.0f / dd;
+}
+
+}  // namespace irgs

@@ -1,0 +1,111 @@
+// Host-side interfaces between the translation units of the HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "irgs_device.hpp"
+
+namespace irgs {
+
+struct BuildArgs {
+    int n;
+    const float* mu;
+    const float* quat;
+    const float* scale;
+    const float* opac;
+    float alpha_min;
+    float sigma;
+    uint32_t* order;        // Morton position -> surfel id
+    uint64_t* sorted_keys;  // optional copy of the sorted Morton codes
+    SurfelRec* rec;
+    float* leafbox;         // 6 floats per Morton position
+    BvhNode* nodes;
+    int* leaf_parent;
+    uint32_t* counters;
+    int* depth;             // device int: max number of internal ancestors of a leaf
+};
+
+hipError_t lbvh_sort_scratch_bytes(int n, size_t* bytes);
+hipError_t lbvh_build(const BuildArgs& a, void* scratch, hipStream_t st);
+hipError_t lbvh_refit(const BuildArgs& a, hipStream_t st);
+
+struct OutPtrs {
+    float* O;
+    float* feat;
+    float* D;
+    float* T;
+    int32_t* n_hits;
+    int32_t* hit_ids;
+    float* hit_T;
+    int32_t H_cap;
+};
+
+struct GradIn {
+    const float* gO;
+    const float* gF;
+    const float* gD;
+};
+
+struct GradOut {
+    float* mu;
+    float* quat;
+    float* scale;
+    float* opac;
+    float* feat;
+};
+
+struct RawSurfels {
+    const float* mu;
+    const float* quat;
+    const float* scale;
+    const float* opac;
+    const float* feat;
+};
+
+// Largest k-buffer / feature count the kernels are instantiated for.
+constexpr int kMaxK = 64;
+constexpr int kMaxF = 64;
+
+// Number of persistent trace threads launched for R rays (grid-stride).
+int64_t trace_threads(int64_t R);
+
+// Forward trace.  use_bvh = false tests every record (the plain tracer).
+// `ovf` is the global stack overflow area: ovf_slots entries per thread of
+// the grid (trace_threads(R) threads), or null when ovf_slots == 0.
+hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,
+                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots,
+                        hipStream_t st);
+
+// Backward.  Store mode reads saved ids and T (rays with n_hits > H_cap are
+// re-marched); recompute mode re-marches every ray.  `ck` is checkpoint
+// scratch of trace_threads(R) * kBwdCheckpoints * 4 words.
+constexpr int kBwdCheckpoints = 8;
+hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int k, int64_t R,
+                           const float* ro, const float* rd, const OutPtrs& saved, bool use_saved,
+                           const GradIn& gin, const GradOut& gout, int* ovf, int ovf_slots, float* ck,
+                           hipStream_t st);
+
+// Packed launch over work items of several scenes (serving).  Item i owns
+// the chunks [chunk_begin, chunk_begin + ceil(ray_count / kBlock)).
+struct WorkItem {
+    int32_t scene;
+    int32_t pad;
+    int64_t ray_begin;
+    int64_t ray_count;
+    int64_t chunk_begin;
+    const float* ro;
+    const float* rd;
+    OutPtrs out;
+};
+
+hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_chunks,
+                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* queue_counter, int grid_blocks,
+                         hipStream_t st);
+
+// Fill n 32-bit words with v (a kernel, so it can be captured in a graph).
+hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);
+
+}  // namespace irgs

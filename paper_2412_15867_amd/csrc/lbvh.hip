@@ -1,0 +1,546 @@
+// Software LBVH over surfel bounding boxes (gfx950).
+//
+// The paper bounds each 2D Gaussian by an icosahedron proxy sized to enclose
+// the region where its alpha reaches alpha_min (Eq. 5) and hands the 20N
+// triangles to a hardware BVH builder, updated every training iteration
+// (Sec. 3.2, implementation details: about 3 ms per update).  CDNA4 has no
+// ray-tracing units, so the same role is played here by a linear BVH built in
+// software:
+//   1. per surfel: record (frame, scaled tangents, support) and the exact box
+//      of its support ellipse  rho <= min(sigma, sqrt(2 ln(o / alpha_min)))
+//      -- the radius of Eq. 5's proxy, capped at sigma;
+//   2. scene bounds of the centres, 63-bit Morton codes (21 bits per axis);
+//   3. stable LSD radix sort of (code, id) -- 8 passes of 8-bit digits,
+//      per-tile histograms, one scan, stable wave-ballot ranking;
+//   4. Karras' hierarchy (longest common prefix of adjacent codes, index
+//      tie-break for equal codes);
+//   5. bottom-up boxes with per-node arrival counters (second arrival unions).
+// Refit repeats 1 (in the existing leaf order) and 5 with the topology kept.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "irgs_device.hpp"
+#include "irgs_internal.hpp"
+
+namespace irgs {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per tile
+constexpr int kRadixBins = 256;
+
+__device__ __forceinline__ bool surfel_valid(float3 m, float4 q, float2 s, float o)
+{
+    const bool fin = isfinite(m.x) && isfinite(m.y) && isfinite(m.z) && isfinite(q.x) && isfinite(q.y) &&
+                     isfinite(q.z) && isfinite(q.w) && isfinite(s.x) && isfinite(s.y) && isfinite(o);
+    const float qq = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+    return fin && qq > 0.0f && isfinite(qq) && s.x > 0.0f && s.y > 0.0f;
+}
+
+__device__ __forceinline__ float3 ld3(const float* p, int64_t i)
+{
+    return make_float3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+}
+__device__ __forceinline__ float4 ld4(const float* p, int64_t i)
+{
+    return make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+}
+__device__ __forceinline__ float2 ld2(const float* p, int64_t i) { return make_float2(p[2 * i], p[2 * i + 1]); }
+
+// ---------------------------------------------------------------- bounds
+__global__ void k_bounds_partial(int n, const float* __restrict__ mu, const float* __restrict__ quat,
+                                 const float* __restrict__ scale, const float* __restrict__ opac,
+                                 float* __restrict__ partial)
+{
+    __shared__ float red[6][kSortThreads];
+    float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float3 m = ld3(mu, i);
+        if (!surfel_valid(m, ld4(quat, i), ld2(scale, i), opac[i])) continue;
+        lo[0] = fminf(lo[0], m.x), lo[1] = fminf(lo[1], m.y), lo[2] = fminf(lo[2], m.z);
+        hi[0] = fmaxf(hi[0], m.x), hi[1] = fmaxf(hi[1], m.y), hi[2] = fmaxf(hi[2], m.z);
+    }
+    for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = lo[k];
+        red[k + 3][threadIdx.x] = hi[k];
+    }
+    __syncthreads();
+    for (int off = kSortThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            for (int k = 0; k < 3; ++k) {
+                red[k][threadIdx.x] = fminf(red[k][threadIdx.x], red[k][threadIdx.x + off]);
+                red[k + 3][threadIdx.x] = fmaxf(red[k + 3][threadIdx.x], red[k + 3][threadIdx.x + off]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_bounds_final(int nparts, const float* __restrict__ partial, float* __restrict__ bounds)
+{
+    if (threadIdx.x >= 6) return;
+    const int k = threadIdx.x;
+    float v = k < 3 ? 3.0e38f : -3.0e38f;
+    for (int b = 0; b < nparts; ++b) v = k < 3 ? fminf(v, partial[b * 6 + k]) : fmaxf(v, partial[b * 6 + k]);
+    bounds[k] = v;
+}
+
+// ---------------------------------------------------------------- morton
+__device__ __forceinline__ uint64_t spread21(uint32_t x)
+{
+    uint64_t v = x & 0x1fffffu;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t quantize21(float x, float lo, float hi)
+{
+    const float ext = hi - lo;
+    if (!(ext > 0.0f)) return 0u;
+    float f = (x - lo) / ext * 2097152.0f;
+    f = fminf(fmaxf(f, 0.0f), 2097151.0f);
+    return static_cast<uint32_t>(f);
+}
+
+__global__ void k_morton(int n, const float* __restrict__ mu, const float* __restrict__ quat,
+                         const float* __restrict__ scale, const float* __restrict__ opac,
+                         const float* __restrict__ bounds, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float3 m = ld3(mu, i);
+    uint64_t key = ~0ull >> 1;  // invalid surfels sort last
+    if (surfel_valid(m, ld4(quat, i), ld2(scale, i), opac[i])) {
+        key = (spread21(quantize21(m.x, bounds[0], bounds[3])) << 2) |
+              (spread21(quantize21(m.y, bounds[1], bounds[4])) << 1) |
+              spread21(quantize21(m.z, bounds[2], bounds[5]));
+    }
+    keys[i] = key;
+    vals[i] = static_cast<uint32_t>(i);
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(int n, int shift, const uint64_t* __restrict__ keys,
+                                                              uint32_t* __restrict__ counts, int ntiles)
+{
+    __shared__ uint32_t h[kRadixBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kSortTile;
+    for (int s = 0; s < kSortItems; ++s) {
+        const int i = base + s * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xff], 1u);
+    }
+    __syncthreads();
+    counts[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `len` counters in one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ data, int len)
+{
+    __shared__ uint32_t part[1024];
+    const int per = (len + 1023) / 1024;
+    const int b = threadIdx.x * per;
+    const int e = min(len, b + per);
+    uint32_t s = 0;
+    for (int i = b; i < e; ++i) s += data[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 partial sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int i = b; i < e; ++i) {
+        const uint32_t c = data[i];
+        data[i] = run;
+        run += c;
+    }
+}
+
+// Stable scatter of one tile: keys are ranked in input order, 256 at a time;
+// inside a wave the rank among equal digits comes from 8 ballots.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(int n, int shift, int ntiles,
+                                                                 const uint64_t* __restrict__ kin,
+                                                                 const uint32_t* __restrict__ vin,
+                                                                 uint64_t* __restrict__ kout,
+                                                                 uint32_t* __restrict__ vout,
+                                                                 const uint32_t* __restrict__ offsets)
+{
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ uint32_t base[kRadixBins];
+    __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    base[threadIdx.x] = offsets[threadIdx.x * ntiles + blockIdx.x];
+    const int tile0 = blockIdx.x * kSortTile;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int s = 0; s < kSortItems; ++s) {
+        for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        const int i = tile0 + s * kSortThreads + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        uint32_t val = 0;
+        uint32_t dg = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            dg = static_cast<uint32_t>((key >> shift) & 0xff);
+        }
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = __popcll(m & lt_mask);
+        if (valid && rank == 0) wcnt[wave][dg] = __popcll(m);
+        __syncthreads();
+        // per digit: exclusive prefix over the waves, then advance the base
+        {
+            const int d = threadIdx.x;
+            uint32_t run = base[d];
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wcnt[w][d];
+                wcnt[w][d] = run;
+                run += c;
+            }
+            base[d] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = wcnt[wave][dg] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- records
+// Record + leaf box of the surfel at Morton position p.
+__global__ void k_records(int n, const uint32_t* __restrict__ order, const float* __restrict__ mu,
+                          const float* __restrict__ quat, const float* __restrict__ scale,
+                          const float* __restrict__ opac, float alpha_min, float sigma,
+                          SurfelRec* __restrict__ rec, float* __restrict__ leafbox)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int i = static_cast<int>(order[p]);
+    const float3 m = ld3(mu, i);
+    const float4 q = ld4(quat, i);
+    const float2 s = ld2(scale, i);
+    const float o = opac[i];
+    float tu[3] = {0, 0, 0}, tv[3] = {0, 0, 0}, nn[3] = {0, 0, 1};
+    float rho2max = -1.0f;
+    const bool ok = surfel_valid(m, q, s, o);
+    if (ok) {
+        quat_frame(q, tu, tv, nn);
+        if (o >= alpha_min) {
+            const float lim = 2.0f * logf(o / alpha_min);
+            rho2max = fminf(sigma * sigma, fmaxf(lim, 0.0f));
+        }
+    }
+    SurfelRec r;
+    r.a = make_float4(m.x, m.y, m.z, o);
+    r.b = make_float4(nn[0], nn[1], nn[2], rho2max);
+    r.c = make_float4(tu[0] / s.x, tu[1] / s.x, tu[2] / s.x, __int_as_float(i));
+    r.d = make_float4(tv[0] / s.y, tv[1] / s.y, tv[2] / s.y, 0.0f);
+    if (!ok) {
+        r.c = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(i));
+        r.d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    rec[p] = r;
+    float* bx = leafbox + 6 * static_cast<int64_t>(p);
+    if (rho2max < 0.0f) {
+        const float inf = __int_as_float(0x7f800000);
+        for (int k = 0; k < 6; ++k) bx[k] = inf;
+        return;
+    }
+    // Box of the ellipse mu + a s_u t_u + b s_v t_v, a^2 + b^2 <= rho^2,
+    // padded so that FP32 rounding in the hit and slab tests can never put a
+    // hit outside it.
+    const float rho = sqrtf(rho2max);
+    const float amax = fmaxf(fmaxf(fabsf(m.x), fabsf(m.y)), fabsf(m.z));
+    const float pad_abs = 1e-5f * (1.0f + amax);
+    for (int k = 0; k < 3; ++k) {
+        const float eu = s.x * tu[k], ev = s.y * tv[k];
+        const float h = rho * sqrtf(eu * eu + ev * ev);
+        const float pad = pad_abs + 1e-4f * rho * fmaxf(s.x, s.y);
+        const float c = k == 0 ? m.x : (k == 1 ? m.y : m.z);
+        bx[k] = c - h - pad;
+        bx[k + 3] = c + h + pad;
+    }
+}
+
+// ---------------------------------------------------------------- Karras
+__device__ __forceinline__ int lcp(const uint64_t* __restrict__ keys, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    const uint64_t a = keys[i], b = keys[j];
+    if (a != b) return __clzll(static_cast<long long>(a ^ b));
+    return 64 + __clz(static_cast<int>(static_cast<uint32_t>(i) ^ static_cast<uint32_t>(j)));
+}
+
+__global__ void k_karras(int n, const uint64_t* __restrict__ keys, BvhNode* __restrict__ nodes,
+                         int* __restrict__ leaf_parent)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (lcp(keys, n, i, i + 1) - lcp(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = lcp(keys, n, i, i - d);
+    int lmax = 2;
+    while (lcp(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (lcp(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = lcp(keys, n, i, j);
+    int s = 0;
+    int t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (lcp(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int g = i + s * d + min(d, 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const int left = (lo == g) ? (g | kLeafBit) : g;
+    const int right = (hi == g + 1) ? ((g + 1) | kLeafBit) : (g + 1);
+    nodes[i].ch.x = left;
+    nodes[i].ch.y = right;
+    if (left & kLeafBit)
+        leaf_parent[g] = i;
+    else
+        nodes[g].ch.z = i;
+    if (right & kLeafBit)
+        leaf_parent[g + 1] = i;
+    else
+        nodes[g + 1].ch.z = i;
+    if (i == 0) nodes[0].ch.z = -1;
+}
+
+__global__ void k_single_root(BvhNode* nodes, int* leaf_parent)
+{
+    const float inf = __int_as_float(0x7f800000);
+    nodes[0].ch = make_int4(0 | kLeafBit, kNoChild, -1, 0);
+    nodes[0].p1.z = inf, nodes[0].p1.w = inf;
+    nodes[0].p2 = make_float4(inf, inf, inf, inf);
+    leaf_parent[0] = 0;
+}
+
+// ---------------------------------------------------------------- boxes
+__device__ __forceinline__ void child_box(const BvhNode& nd, int which, float* b)
+{
+    if (which == 0) {
+        b[0] = nd.p0.x, b[1] = nd.p0.y, b[2] = nd.p0.z, b[3] = nd.p0.w, b[4] = nd.p1.x, b[5] = nd.p1.y;
+    } else {
+        b[0] = nd.p1.z, b[1] = nd.p1.w, b[2] = nd.p2.x, b[3] = nd.p2.y, b[4] = nd.p2.z, b[5] = nd.p2.w;
+    }
+}
+
+__device__ __forceinline__ bool box_empty(const float* b) { return isinf(b[0]) && b[0] > 0.0f; }
+
+// Union of the two child boxes stored in `nd` (empty boxes are skipped).
+__device__ __forceinline__ void node_union(const BvhNode& nd, float* out)
+{
+    float a[6], b[6];
+    child_box(nd, 0, a);
+    child_box(nd, 1, b);
+    const bool ea = nd.ch.x == kNoChild || box_empty(a);
+    const bool eb = nd.ch.y == kNoChild || box_empty(b);
+    for (int k = 0; k < 6; ++k) {
+        if (ea && eb)
+            out[k] = __int_as_float(0x7f800000);
+        else if (ea)
+            out[k] = b[k];
+        else if (eb)
+            out[k] = a[k];
+        else
+            out[k] = k < 3 ? fminf(a[k], b[k]) : fmaxf(a[k], b[k]);
+    }
+}
+
+__device__ __forceinline__ void store_child_box(BvhNode* nd, int which, const float* b)
+{
+    float* f = reinterpret_cast<float*>(nd);
+    const int o = which == 0 ? 0 : 6;
+    for (int k = 0; k < 6; ++k) __hip_atomic_store(f + o + k, b[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ BvhNode load_node_coherent(BvhNode* nd)
+{
+    BvhNode r;
+    float* f = reinterpret_cast<float*>(nd);
+    float* o = reinterpret_cast<float*>(&r);
+    for (int k = 0; k < 12; ++k) o[k] = __hip_atomic_load(f + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.ch = nd->ch;
+    return r;
+}
+
+// Each leaf walks up; the second thread to arrive at a node writes the
+// node's box into its parent's slot and continues, the first one stops.
+__global__ void k_bottom_up(int n, const float* __restrict__ leafbox, BvhNode* nodes,
+                            const int* __restrict__ leaf_parent, uint32_t* counters)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    float b[6];
+    for (int k = 0; k < 6; ++k) b[k] = leafbox[6 * static_cast<int64_t>(p) + k];
+    int child = p | kLeafBit;
+    int node = leaf_parent[p];
+    while (node >= 0) {
+        const int which = (nodes[node].ch.x == child) ? 0 : 1;
+        store_child_box(&nodes[node], which, b);
+        const uint32_t prev =
+            __hip_atomic_fetch_add(&counters[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const bool single = nodes[node].ch.y == kNoChild;
+        if (prev == 0 && !single) return;  // first arrival: the sibling finishes this node
+        const BvhNode nd = load_node_coherent(&nodes[node]);
+        node_union(nd, b);
+        child = node;
+        node = nd.ch.z;
+    }
+}
+
+__global__ void k_depth(int n, const int* __restrict__ leaf_parent, const BvhNode* __restrict__ nodes,
+                        int* __restrict__ depth_out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int d = 0;
+    int node = leaf_parent[p];
+    while (node >= 0) {
+        ++d;
+        node = nodes[node].ch.z;
+    }
+    atomicMax(depth_out, d);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
+{
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+inline int blocks_for(int64_t n, int t) { return static_cast<int>((n + t - 1) / t); }
+
+
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int nb = static_cast<int>(n < 256 * 1024 ? (n + 255) / 256 : 1024);
+    k_fill_u32<<<nb, 256, 0, st>>>(static_cast<uint32_t*>(p), n, v);
+    return hipGetLastError();
+}
+
+hipError_t lbvh_sort_scratch_bytes(int n, size_t* bytes)
+{
+    const int ntiles = blocks_for(n, kSortTile);
+    *bytes = static_cast<size_t>(n) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) +
+             static_cast<size_t>(ntiles) * kRadixBins * sizeof(uint32_t) + 64 * 6 * sizeof(float) + 256;
+    return hipSuccess;
+}
+
+// Records + leaf boxes in the current leaf order, then bottom-up boxes.
+static hipError_t refit_boxes(const BuildArgs& a, hipStream_t st)
+{
+    const int n = a.n;
+    k_records<<<blocks_for(n, 256), 256, 0, st>>>(n, a.order, a.mu, a.quat, a.scale, a.opac, a.alpha_min,
+                                                    a.sigma, a.rec, a.leafbox);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nint = n > 1 ? n - 1 : 1;
+    e = fill_u32(a.counters, nint, 0u, st);
+    if (e != hipSuccess) return e;
+    k_bottom_up<<<blocks_for(n, 256), 256, 0, st>>>(n, a.leafbox, a.nodes, a.leaf_parent, a.counters);
+    return hipGetLastError();
+}
+
+hipError_t lbvh_build(const BuildArgs& a, void* scratch, hipStream_t st)
+{
+    const int n = a.n;
+    if (n <= 0) return hipSuccess;
+    const int ntiles = blocks_for(n, kSortTile);
+    char* p = static_cast<char*>(scratch);
+    uint64_t* k0 = reinterpret_cast<uint64_t*>(p);
+    p += sizeof(uint64_t) * n;
+    uint64_t* k1 = reinterpret_cast<uint64_t*>(p);
+    p += sizeof(uint64_t) * n;
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(p);
+    p += sizeof(uint32_t) * n;
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(p);
+    p += sizeof(uint32_t) * n;
+    uint32_t* counts = reinterpret_cast<uint32_t*>(p);
+    p += sizeof(uint32_t) * ntiles * kRadixBins;
+    float* partial = reinterpret_cast<float*>(p);
+    p += sizeof(float) * 6 * 64;
+    float* bounds = reinterpret_cast<float*>(p);
+
+    k_bounds_partial<<<64, kSortThreads, 0, st>>>(n, a.mu, a.quat, a.scale, a.opac, partial);
+    k_bounds_final<<<1, 64, 0, st>>>(64, partial, bounds);
+    k_morton<<<blocks_for(n, 256), 256, 0, st>>>(n, a.mu, a.quat, a.scale, a.opac, bounds, k0, v0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = pass * 8;
+        k_radix_hist<<<ntiles, kSortThreads, 0, st>>>(n, shift, k0, counts, ntiles);
+        k_scan_exclusive<<<1, 1024, 0, st>>>(counts, ntiles * kRadixBins);
+        k_radix_scatter<<<ntiles, kSortThreads, 0, st>>>(n, shift, ntiles, k0, v0, k1, v1, counts);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t* tk = k0;
+        k0 = k1;
+        k1 = tk;
+        uint32_t* tv = v0;
+        v0 = v1;
+        v1 = tv;
+    }
+    // after an even number of passes the sorted data is back in k0/v0
+    e = hipMemcpyAsync(a.order, v0, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    if (a.sorted_keys) {
+        e = hipMemcpyAsync(a.sorted_keys, k0, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    const int nint = n > 1 ? n - 1 : 1;
+    e = fill_u32(a.nodes, static_cast<int64_t>(nint) * (sizeof(BvhNode) / 4), 0u, st);
+    if (e != hipSuccess) return e;
+    if (n == 1) {
+        k_single_root<<<1, 1, 0, st>>>(a.nodes, a.leaf_parent);
+    } else {
+        k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(n, k0, a.nodes, a.leaf_parent);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = refit_boxes(a, st);
+    if (e != hipSuccess) return e;
+    e = fill_u32(a.depth, 1, 0u, st);
+    if (e != hipSuccess) return e;
+    k_depth<<<blocks_for(n, 256), 256, 0, st>>>(n, a.leaf_parent, a.nodes, a.depth);
+    return hipGetLastError();
+}
+
+hipError_t lbvh_refit(const BuildArgs& a, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    return refit_boxes(a, st);
+}
+
+}  // namespace irgs

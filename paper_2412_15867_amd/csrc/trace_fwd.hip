@@ -1,0 +1,226 @@
+// Forward 2D Gaussian ray tracing (Sec. 3.2, Eq. 2, 6-8) on gfx950.
+//
+// One lane traces one ray; a persistent grid strides over the rays.  Each
+// k-buffer round collects the K nearest hits after the resume key (by BVH
+// traversal, or by testing every record in the plain tracer), then
+// composites them front to back in registers:
+//     w = T alpha;  O += w;  F += w f;  D += w tau;  T *= (1 - alpha)
+// and stops once T < T_min (the hit that crosses the cutoff is included).
+// A round with fewer than K hits is the last one.
+#include <hip/hip_runtime.h>
+
+#include "irgs_internal.hpp"
+#include "march.hpp"
+
+namespace irgs {
+
+int64_t trace_threads(int64_t R)
+{
+    constexpr int64_t kMaxBlocks = 256 * 8;  // 256 CUs x 8 resident blocks
+    int64_t blocks = (R + kBlock - 1) / kBlock;
+    if (blocks > kMaxBlocks) blocks = kMaxBlocks;
+    if (blocks < 1) blocks = 1;
+    return blocks * kBlock;
+}
+
+namespace {
+
+template <int K, int FM, bool BVH>
+__device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams& P, const Ray& ray, int64_t r,
+                                          const OutPtrs& out, Stack& st)
+{
+    float T = 1.0f, O = 0.0f, D = 0.0f;
+    float acc[FM];
+#pragma unroll
+    for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
+    int nh = 0;
+    if (sc.n > 0 && ray_valid(ray)) {
+        const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
+        float last_t = -__int_as_float(0x7f800000);
+        int last_i = -1;
+        bool done = false;
+        while (!done) {
+            KBuf<K> kb;
+            kb.clear();
+            if (BVH)
+                collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st);
+            else
+                collect_all<K>(kb, sc, ray, P.t_min, P.t_max, last_t, last_i);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (j < kb.cnt && !done) {
+                    const float a = kb.a[j];
+                    const float w = T * a;
+                    const int id = kb.id[j];
+                    O += w;
+                    D = fmaf(w, kb.t[j], D);
+                    const float* f = sc.feat + static_cast<int64_t>(id) * P.F;
+#pragma unroll
+                    for (int c = 0; c < FM; ++c)
+                        if (c < P.F) acc[c] = fmaf(w, f[c], acc[c]);
+                    if (out.hit_ids && nh < out.H_cap) {
+                        out.hit_ids[r * out.H_cap + nh] = id;
+                        if (out.hit_T) out.hit_T[r * out.H_cap + nh] = T;
+                    }
+                    T = T * (1.0f - a);
+                    ++nh;
+                    if (T < P.T_min) done = true;
+                }
+            }
+            if (kb.cnt < K) {
+                done = true;
+            } else {
+                last_t = kb.t[K - 1];
+                last_i = kb.id[K - 1];
+            }
+        }
+    }
+    out.O[r] = O;
+    out.D[r] = D;
+#pragma unroll
+    for (int c = 0; c < FM; ++c)
+        if (c < P.F) out.feat[r * P.F + c] = acc[c];
+    if (out.T) out.T[r] = T;
+    if (out.n_hits) out.n_hits[r] = nh;
+}
+
+template <int K, int FM, bool BVH>
+__global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, int64_t R,
+                                                  const float* __restrict__ ro, const float* __restrict__ rd,
+                                                  OutPtrs out, int* ovf, int ovf_slots)
+{
+    __shared__ int lds_stack[BVH ? kStackLds * kBlock : 1];
+    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
+    Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
+             0};
+    for (int64_t r = gtid; r < R; r += nthr) {
+        const Ray ray = load_ray(ro, rd, r);
+        trace_one<K, FM, BVH>(sc, P, ray, r, out, st);
+    }
+}
+
+template <int K, int FM, bool BVH>
+hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
+                     const OutPtrs& out, int* ovf, int ovf_slots, hipStream_t st)
+{
+    const int64_t nthr = trace_threads(R);
+    k_trace<K, FM, BVH><<<static_cast<unsigned>(nthr / kBlock), kBlock, 0, st>>>(sc, P, R, ro, rd, out, ovf,
+                                                                                 ovf_slots);
+    return hipGetLastError();
+}
+
+template <int K, bool BVH>
+hipError_t launch_k(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
+                    const OutPtrs& out, int* ovf, int ovf_slots, hipStream_t st)
+{
+    if (P.F <= 4) return launch_kf<K, 4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+    if (P.F <= 8) return launch_kf<K, 8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+    if constexpr (K == 16 || K == 32) {
+        if (P.F <= 16) return launch_kf<K, 16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        if (P.F <= 64) return launch_kf<K, 64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <bool BVH>
+hipError_t launch_b(const SceneView& sc, const TraceParams& P, int k, int64_t R, const float* ro, const float* rd,
+                    const OutPtrs& out, int* ovf, int ovf_slots, hipStream_t st)
+{
+    switch (k) {
+        case 1: return launch_k<1, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        case 2: return launch_k<2, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        case 4: return launch_k<4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        case 8: return launch_k<8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        case 16: return launch_k<16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        case 32: return launch_k<32, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        case 64: return launch_k<64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Packed persistent launch: every block repeatedly takes the next chunk of
+// kBlock rays from a device counter; a chunk belongs to one work item (one
+// request of one scene), so different requests and scenes share a launch.
+// The loop ends for every block once the counter passes n_chunks.
+template <int K, int FM>
+__global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__ scenes,
+                                                   const WorkItem* __restrict__ items, int n_items,
+                                                   int64_t n_chunks, TraceParams P, int* ovf, int ovf_slots,
+                                                   int* counter)
+{
+    __shared__ int lds_stack[kStackLds * kBlock];
+    __shared__ int s_chunk;
+    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
+    Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
+             0};
+    while (true) {
+        if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1);
+        __syncthreads();
+        const int64_t c = s_chunk;
+        __syncthreads();
+        if (c >= n_chunks) break;
+        // the item owning chunk c: last item with chunk_begin <= c
+        int lo = 0, hi = n_items - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].chunk_begin <= c)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const WorkItem& it = items[lo];
+        const SceneView sc = scenes[it.scene];
+        TraceParams Pi = P;
+        Pi.F = sc.F;
+        const int64_t local = (c - it.chunk_begin) * kBlock + threadIdx.x;
+        if (local < it.ray_count) {
+            const int64_t r = it.ray_begin + local;
+            const Ray ray = load_ray(it.ro, it.rd, r);
+            trace_one<K, FM, true>(sc, Pi, ray, r, it.out, st);
+        }
+    }
+}
+
+template <int K, int FM>
+hipError_t launch_packed_kf(const SceneView* scenes, const WorkItem* items, int n_items, int64_t n_chunks,
+                            const TraceParams& P, int* ovf, int ovf_slots, int* counter, int grid_blocks,
+                            hipStream_t st)
+{
+    k_packed<K, FM><<<grid_blocks, kBlock, 0, st>>>(scenes, items, n_items, n_chunks, P, ovf, ovf_slots, counter);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_chunks,
+                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* queue_counter, int grid_blocks,
+                         hipStream_t st)
+{
+    if (n_chunks <= 0 || n_items <= 0) return hipSuccess;
+    if (k == 16 && P.F <= 8)
+        return launch_packed_kf<16, 8>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+                                       grid_blocks, st);
+    if (k == 16 && P.F <= 64)
+        return launch_packed_kf<16, 64>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+                                        grid_blocks, st);
+    if (k == 32 && P.F <= 8)
+        return launch_packed_kf<32, 8>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+                                       grid_blocks, st);
+    if (k == 32 && P.F <= 64)
+        return launch_packed_kf<32, 64>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+                                        grid_blocks, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,
+                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots,
+                        hipStream_t st)
+{
+    if (R <= 0) return hipSuccess;
+    return use_bvh ? launch_b<true>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, st)
+                   : launch_b<false>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, st);
+}
+
+}  // namespace irgs

@@ -1,0 +1,170 @@
+"""Backward parity of the HIP adjoint against the FP64 gradient oracle
+(autograd over the same hit lists) and finite differences; store and
+re-march modes; the torch.autograd.Function wrapper."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import grad as ograd
+from paper_2412_15867_amd import synth
+from gpu_util import dev, make_scene, note, to_np
+from validate import validate
+
+pytestmark = pytest.mark.gpu
+
+NAMES = (("mu", "mu"), ("quat", "quat"), ("scale", "scale"), ("opacity", "opac"), ("feat", "feat"))
+
+
+def grad_close(g_gpu, g_ref, rel=1e-3):
+    """|d| <= rel (|g_ref| + mean |g_ref| of the group), per parameter group."""
+    worst = {}
+    for name, key in NAMES:
+        a = g_gpu[name].reshape(g_ref[key].shape)
+        b = g_ref[key]
+        floor = np.abs(b).mean() + 1e-30
+        err = np.abs(a - b) / (np.abs(b) + floor)
+        worst[name] = float(err.max())
+        assert err.max() <= rel, (name, err.max())
+    return worst
+
+
+def gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=256, recompute=False, k=16, T_min=1e-4):
+    from paper_2412_15867_amd import TraceConfig, trace, trace_backward
+    scene = make_scene(surf)
+    cfg = TraceConfig(k=k, T_min=T_min, recompute=recompute)
+    res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=hit_cap)
+    grads = trace_backward(scene, dev(ro), dev(rd), res, dev(gO), dev(gF), dev(gD), cfg=cfg)
+    torch.cuda.synchronize()
+    out = {k2: v.cpu().numpy().astype(np.float64) for k2, v in grads.items()}
+    fwd = to_np(res)
+    scene.close()
+    return fwd, out
+
+
+def lists_of(fwd):
+    H = fwd["hit_ids"].shape[1]
+    return np.where(np.arange(H)[None, :] < fwd["n_hits"][:, None], fwd["hit_ids"], -1)
+
+
+@pytest.fixture(scope="module")
+def cube():
+    sc = synth.cube_scene()
+    ro, rd = synth.pinhole_rays(32, 32)
+    gO, gF, gD, _ = synth.upstream(ro.shape[0], sc.F)
+    return sc, ro, rd, gO, gF, gD
+
+
+def test_cube_gradients_match_fp64_oracle(cube):
+    sc, ro, rd, gO, gF, gD = cube
+    note("cube backward store")
+    fwd, g = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD)
+    validate(sc.astuple(), ro, rd, fwd)
+    ref = ograd.grad_given_hits(sc.astuple(), ro, rd, lists_of(fwd), gO, gF, gD)
+    w = grad_close(g, ref)
+    note(f"cube worst rel err {w}")
+
+
+def test_recompute_equals_store(cube):
+    sc, ro, rd, gO, gF, gD = cube
+    note("cube backward recompute")
+    _, a = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD)
+    _, b = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD, hit_cap=0, recompute=True)
+    for name, _ in NAMES:
+        np.testing.assert_allclose(a[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(a[name]).max())
+
+
+def test_small_hit_cap_falls_back_to_recompute(cube):
+    """Rays with more hits than the stored capacity re-march."""
+    sc, ro, rd, gO, gF, gD = cube
+    note("cube backward hit_cap 4")
+    fwd, a = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD, hit_cap=4)
+    assert np.mean(fwd["n_hits"] > 4) > 0.2
+    _, b = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD, hit_cap=256)
+    for name, _ in NAMES:
+        np.testing.assert_allclose(a[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
+
+
+def test_many_rounds_past_the_checkpoints():
+    """k = 1 on 60 coaxial splats: 42 rounds, more than the 8 stored round
+    checkpoints, in re-march mode; closed-form and oracle gradients."""
+    n = 60
+    g = np.random.default_rng(30)
+    perm = g.permutation(n)
+    mu = np.stack([g.normal(0, 0.01, n), g.normal(0, 0.01, n), -0.05 * np.arange(n)], 1)[perm].astype(np.float32)
+    q = np.tile(np.float32([1, 0, 0, 0]), (n, 1)) + g.normal(0, 0.05, (n, 4)).astype(np.float32)
+    s = np.full((n, 2), 0.1, np.float32)
+    o = np.full(n, 0.2, np.float32)
+    f = g.uniform(0, 1, (n, 3)).astype(np.float32)
+    ro = np.float32([[0, 0, 1.0], [0.01, 0.02, 1.0]])
+    rd = np.float32([[0, 0, -1.0], [0, 0, -1.0]])
+    gO, gF, gD = np.float32([1, -0.5]), np.float32([[0.3, 0.2, 0.1], [1, 1, 1]]), np.float32([0.7, 0.1])
+    surf = (mu, q, s, o, f)
+    note("deep rays k=1 recompute")
+    fwd, a = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=64, recompute=True, k=1)
+    assert np.all(fwd["n_hits"] > 30)
+    ref = ograd.grad_given_hits(surf, ro, rd, lists_of(fwd), gO, gF, gD)
+    grad_close(a, ref)
+    _, b = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=64, recompute=False, k=16)
+    for name, _ in NAMES:
+        np.testing.assert_allclose(a[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
+
+
+def test_finite_differences_on_surface_patch():
+    """256 surfels nearest a surface point of the 1M-surfel scene, 1,024 rays
+    aimed at the patch: GPU gradients vs FP64 central differences of the
+    brute-force oracle (perturbations that change a hit list are skipped)."""
+    lay = synth.layout()
+    big, sid = synth.surface_scene(1_000_000, F=8, lay=lay, return_surface_id=True)
+    g = np.random.default_rng(31)
+    # a sphere patch: plane patches are coplanar up to FP32 rounding of the
+    # inputs, where any perturbation reorders near-tied hits
+    c = big.mu[g.choice(np.nonzero(sid < 8)[0])].astype(np.float64)
+    d2 = np.sum((big.mu.astype(np.float64) - c) ** 2, 1)
+    idx = np.argsort(d2)[:256]
+    sub = big.subset(idx)
+    rad = float(np.sqrt(d2[idx[-1]]))
+    ro, rd = synth.random_rays_near(g, c, rad, 1024, dist=0.5)
+    gO, gF, gD, _ = synth.upstream(1024, 8, seed=32)
+    note("fd patch gpu")
+    fwd, a = gpu_fwd_bwd(sub.astuple(), ro, rd, gO, gF, gD, hit_cap=256)
+    validate(sub.astuple(), ro, rd, fwd)
+    ref = ograd.grad_given_hits(sub.astuple(), ro, rd, lists_of(fwd), gO, gF, gD)
+    grad_close(a, ref)
+    # finite differences on the first 48 surfels (every parameter of each)
+    keep = np.arange(48)
+    surf = [np.array(x, dtype=np.float64) for x in sub.astuple()]
+    note("fd patch finite differences")
+    fd, skipped = ograd.fd_grad(surf, ro, rd, gO, gF, gD, hit_cap=512, surfel_idx=keep, rel_h=1e-8)
+    total = 48 * 18
+    assert skipped < 0.5 * total, skipped
+    for name, key in NAMES:
+        fv = fd[key].reshape(fd[key].shape[0], -1)[keep]
+        av = a[name].reshape(a[name].shape[0], -1)[keep]
+        m = ~np.isnan(fv)
+        floor = np.abs(fv[m]).mean() + 1e-30
+        err = np.abs(av[m] - fv[m]) / (np.abs(fv[m]) + floor)
+        assert err.max() <= 2e-3, (name, err.max())
+    note(f"fd skipped {skipped}")
+
+
+def test_autograd_function_matches_direct_backward(cube):
+    from paper_2412_15867_amd import TraceConfig, TraceFn, trace, trace_backward
+    sc, ro, rd, gO, gF, gD = cube
+    note("TraceFn")
+    params = [dev(x).requires_grad_(True) for x in sc.astuple()]
+    from paper_2412_15867_amd import Scene
+    scene = Scene(*[p.detach() for p in params])
+    # the scene must wrap the very tensors autograd differentiates
+    scene.set_params(*params)
+    cfg = TraceConfig(k=16)
+    O, F, D = TraceFn.apply(*params, dev(ro), dev(rd), scene, cfg)
+    loss = (O * dev(gO)).sum() + (F * dev(gF)).sum() + (D * dev(gD)).sum()
+    loss.backward()
+    res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=64)
+    direct = trace_backward(scene, dev(ro), dev(rd), res, dev(gO), dev(gF), dev(gD), cfg=cfg)
+    for p, name in zip(params, ("mu", "quat", "scale", "opacity", "feat")):
+        torch.testing.assert_close(p.grad, direct[name].reshape(p.shape), rtol=1e-4, atol=1e-5)
+    scene.close()

@@ -1,0 +1,263 @@
+"""Forward parity of the HIP tracer against the FP64 oracle, through the C ABI
+(Sec. 3.2: Eq. 6-8 with k-buffer marching)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2412_15867_amd import synth
+from gpu_util import dev, make_scene, note, to_np
+from validate import validate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c1():
+    sc = synth.cube_scene()
+    ro, rd = synth.pinhole_rays(64, 64)
+    return sc, ro, rd
+
+
+def run(scene_np, ro, rd, hit_cap=256, **kw):
+    from paper_2412_15867_amd import trace
+    scene = make_scene(scene_np, **{k: kw.pop(k) for k in ("alpha_min", "support_sigma") if k in kw})
+    res = trace(scene, dev(ro), dev(rd), hit_cap=hit_cap, **kw)
+    torch.cuda.synchronize()
+    out = to_np(res)
+    scene.close()
+    return out
+
+
+def test_c1_bvh_matches_oracle(c1):
+    """4,096-surfel cube, 64x64 pinhole rays: every ray accepted by the
+    validation procedure; unambiguous rays reproduce the oracle's list."""
+    sc, ro, rd = c1
+    note("c1 bvh trace k=16")
+    g = run(sc, ro, rd, k=16)
+    st = validate(sc.astuple(), ro, rd, g)
+    note(f"c1 stats {st}")
+    assert st["exact_eligible"] > 0.9 * st["rays"]
+    assert st["hits"] > 10000
+
+
+def test_c1_brute_force_equals_bvh_bitwise(c1):
+    sc, ro, rd = c1
+    note("c1 brute vs bvh")
+    a = run(sc, ro, rd, k=16, brute_force=True)
+    b = run(sc, ro, rd, k=16)
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(a[key], b[key]), key
+    m = np.arange(256)[None, :] < a["n_hits"][:, None]
+    assert np.array_equal(np.where(m, a["hit_ids"], -1), np.where(m, b["hit_ids"], -1))
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 32, 64])
+def test_k_does_not_change_the_result(c1, k):
+    """Exact order + per-hit termination make the output independent of k
+    (bitwise: the same hits are composited in the same order)."""
+    sc, ro, rd = c1
+    note(f"c1 k={k}")
+    a = run(sc, ro, rd, k=16, hit_cap=0)
+    b = run(sc, ro, rd, k=k, hit_cap=0)
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(a[key], b[key]), (k, key)
+
+
+def test_lone_splat_closed_form():
+    """A ray through a lone splat's centre returns exactly its opacity."""
+    g = np.random.default_rng(20)
+    n_rays = 64
+    for trial in range(4):
+        mu = g.uniform(-1, 1, 3)
+        q = g.standard_normal(4)
+        s = np.exp(g.uniform(math.log(0.01), math.log(0.1), 2))
+        o = g.uniform(0.05, 1.0)
+        f = g.uniform(0, 1, 3)
+        S = [np.asarray(x, np.float32).reshape(1, -1) for x in (mu, q, s, f)]
+        surf = (S[0], S[1], S[2], np.asarray([o], np.float32), S[3])
+        d = g.standard_normal((n_rays, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        ro = surf[0].astype(np.float64) - 2.0 * d
+        _, _, nrm = oracle.frames(surf[1])
+        steep = np.abs(d @ nrm[0]) > 0.3
+        note(f"lone splat trial {trial}")
+        r = run(surf, ro.astype(np.float32), d.astype(np.float32), hit_cap=4)
+        ok = steep
+        assert np.all(r["n_hits"][ok] == 1)
+        assert np.all(r["O"][ok] == np.float32(o))
+        np.testing.assert_allclose(r["F"][ok], np.broadcast_to(np.float32(o) * surf[4][0], r["F"][ok].shape),
+                                   rtol=1e-6)
+        np.testing.assert_allclose(r["D"][ok], o * 2.0, rtol=1e-5)
+
+
+def test_parallel_stack_many_rounds():
+    """60 coaxial splats with o = 0.2 crossed through their centres: 42 hits
+    in depth order (3 rounds at k = 16), T = 0.8^42."""
+    n = 60
+    g = np.random.default_rng(21)
+    perm = g.permutation(n)
+    mu = np.stack([np.zeros(n), np.zeros(n), -0.05 * np.arange(n)], 1)[perm].astype(np.float32)
+    q = np.tile(np.float32([1, 0, 0, 0]), (n, 1))
+    s = np.full((n, 2), 0.1, np.float32)
+    o = np.full(n, 0.2, np.float32)
+    f = g.uniform(0, 1, (n, 3)).astype(np.float32)
+    ro = np.float32([[0, 0, 1.0]])
+    rd = np.float32([[0, 0, -1.0]])
+    note("parallel stack")
+    for k in (1, 16, 64):
+        r = run((mu, q, s, o, f), ro, rd, hit_cap=64, k=k)
+        assert r["n_hits"][0] == 42
+        np.testing.assert_array_equal(r["hit_ids"][0, :42], np.argsort(-mu[:, 2], kind="stable")[:42])
+        np.testing.assert_allclose(r["T"][0], 0.8 ** 42, rtol=1e-5)
+        np.testing.assert_allclose(r["O"][0], 1 - 0.8 ** 42, rtol=1e-6)
+
+
+def test_empty_scene_zero_rays_and_invalid_rays(c1):
+    sc, ro, rd = c1
+    from paper_2412_15867_amd import Scene, trace
+    e = [torch.zeros((0, k), device="cuda") for k in (3, 4, 2)] + [torch.zeros(0, device="cuda"),
+                                                                  torch.zeros((0, 3), device="cuda")]
+    note("empty scene")
+    scene = Scene(*e)
+    r = trace(scene, dev(ro[:100]), dev(rd[:100]), hit_cap=4)
+    torch.cuda.synchronize()
+    assert torch.all(r.opacity == 0) and torch.all(r.T == 1) and torch.all(r.n_hits == 0)
+    scene.close()
+    note("zero rays and invalid rays")
+    scene = make_scene(sc)
+    r0 = trace(scene, torch.zeros((0, 3), device="cuda"), torch.zeros((0, 3), device="cuda"))
+    assert r0.opacity.numel() == 0
+    bad_o = np.float32([[np.nan, 0, 3], [0, 0, 3], [0, 0, 3], [np.inf, 0, 3]])
+    bad_d = np.float32([[0, 0, -1], [0, 0, 0], [0, np.nan, -1], [0, 0, -1]])
+    r = to_np(trace(scene, dev(bad_o), dev(bad_d), hit_cap=4))
+    assert np.all(r["O"] == 0) and np.all(r["T"] == 1) and np.all(r["n_hits"] == 0) and np.all(r["F"] == 0)
+    scene.close()
+
+
+def test_degenerate_surfels_never_hit():
+    """NaN centre, zero quaternion, non-positive scale and o < alpha_min are
+    never hit; the rest of the scene still matches the oracle."""
+    sc = synth.cube_scene(2048, seed=5)
+    mu, q, s, o, f = (a.copy() for a in sc.astuple())
+    mu[0] = np.nan
+    q[1] = 0
+    s[2, 0] = 0
+    s[3, 1] = -0.05
+    o[4] = 1.0 / 255.0 * 0.5
+    q[5] *= 1e-3          # tiny but valid quaternion: normalised inside
+    ro, rd = synth.pinhole_rays(32, 32)
+    note("degenerate surfels")
+    g = run((mu, q, s, o, f), ro, rd, hit_cap=256)
+    for bad in range(5):
+        assert not np.any(g["hit_ids"][np.arange(256)[None, :] < g["n_hits"][:, None]] == bad)
+    validate((mu, q, s, o, f), ro, rd, g)
+
+
+def test_permutation_invariance(c1):
+    sc, ro, rd = c1
+    perm = np.random.default_rng(22).permutation(sc.n)
+    note("permutation")
+    a = run(sc, ro, rd, hit_cap=256)
+    b = run(sc.permuted(perm), ro, rd, hit_cap=256)
+    np.testing.assert_allclose(a["O"], b["O"], atol=1e-6)
+    np.testing.assert_allclose(a["F"], b["F"], atol=1e-6)
+    same = np.array_equal(a["n_hits"], b["n_hits"])
+    assert same
+    m = np.arange(256)[None, :] < a["n_hits"][:, None]
+    mapped = np.where(m, perm[np.maximum(b["hit_ids"], 0)], -1)
+    assert np.mean(np.all(np.where(m, a["hit_ids"], -1) == mapped, axis=1)) > 0.999
+
+
+def test_tmin_tmax_window(c1):
+    sc, ro, rd = c1
+    note("t window")
+    g = run(sc, ro, rd, hit_cap=256, t_min=2.5, t_max=3.5)
+    validate(sc.astuple(), ro, rd, g, t_min=2.5, t_max=3.5)
+    assert np.all(g["n_hits"][g["O"] == 0] == 0)
+
+
+def test_paper_cutoff_003(c1):
+    """The paper's transmittance cutoff 0.03."""
+    sc, ro, rd = c1
+    note("T_min 0.03")
+    g = run(sc, ro, rd, hit_cap=256, T_min=0.03)
+    validate(sc.astuple(), ro, rd, g, T_min=0.03)
+
+
+@pytest.fixture(scope="module")
+def surface200k():
+    lay = synth.layout()
+    sc = synth.surface_scene(200_000, F=8, lay=lay)
+    ro, rd = synth.mc_rays(256 * 256, 64, lay=lay)
+    return sc, ro, rd
+
+
+def test_surface_200k_full_launch_sampled(surface200k):
+    """200K surfels, all 4.2M Monte Carlo rays traced in one launch; a seeded
+    sample of 768 rays is validated against the brute-force oracle."""
+    sc, ro, rd = surface200k
+    note("surface 200k full launch")
+    g = run(sc, ro, rd, hit_cap=512)
+    assert np.all(g["n_hits"] <= 512)
+    idx = np.sort(np.random.default_rng(23).choice(ro.shape[0], 768, replace=False))
+    st = validate(sc.astuple(), ro, rd, g, rays=idx)
+    note(f"surface200k stats {st}")
+    frac_hit = np.mean(g["n_hits"] > 0)
+    assert 0.05 < frac_hit < 1.0
+
+
+def test_lbvh_structure(surface200k):
+    """Every leaf is reached exactly once from the root, parents are
+    consistent, node boxes contain their children's boxes and each leaf box
+    contains its surfel's support ellipse."""
+    sc, _, _ = surface200k
+    small = sc.subset(np.arange(0, 200_000, 7))
+    note("lbvh structure")
+    scene = make_scene(small)
+    order, nodes, parent = (t.cpu().numpy() for t in scene.export())
+    info = scene.info()
+    scene.close()
+    n = small.n
+    assert np.array_equal(np.sort(order), np.arange(n))
+    boxes = nodes[:, :12].view(np.float32).astype(np.float64).reshape(-1, 2, 6)
+    ch = nodes[:, 12:14]
+    par = nodes[:, 14]
+    seen = np.zeros(n, np.int64)
+    depth_max = 0
+    stack = [(0, 0)]
+    while stack:
+        nd, dpt = stack.pop()
+        for c in range(2):
+            ref = int(ch[nd, c])
+            if ref < 0 and (ref & 0x7fffffff) < n:
+                leaf = ref & 0x7fffffff
+                seen[leaf] += 1
+                assert parent[leaf] == nd
+                depth_max = max(depth_max, dpt + 1)
+            else:
+                assert par[ref] == nd
+                sub = boxes[ref]
+                box = boxes[nd, c]
+                assert np.all(sub[:, :3] >= box[:3] - 1e-6) and np.all(sub[:, 3:] <= box[3:] + 1e-6)
+                stack.append((ref, dpt + 1))
+    assert np.all(seen == 1)
+    assert depth_max == info["max_depth"]
+    # leaf boxes contain the support ellipse (sampled boundary points)
+    tu, tv, _ = oracle.frames(small.quat)
+    mu = small.mu.astype(np.float64)
+    s = small.scale.astype(np.float64)
+    rho = np.sqrt(np.minimum(9.0, 2 * np.log(small.opac.astype(np.float64) * 255.0)))
+    leaf_box = np.zeros((n, 6))
+    for nd in range(n - 1):
+        for c in range(2):
+            ref = int(ch[nd, c])
+            if ref < 0:
+                leaf_box[ref & 0x7fffffff] = boxes[nd, c]
+    lb = leaf_box[np.argsort(order)]    # by surfel id
+    ang = np.linspace(0, 2 * np.pi, 16, endpoint=False)
+    for a in ang:
+        pts = mu + rho[:, None] * (np.cos(a) * s[:, :1] * tu + np.sin(a) * s[:, 1:] * tv)
+        assert np.all(pts >= lb[:, :3]) and np.all(pts <= lb[:, 3:])
