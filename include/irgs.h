@@ -101,6 +101,8 @@ typedef struct {
  *                    optional; entries past n_hits are left untouched
  *   hit_T (R x H_cap)    transmittance before each of those hits, optional
  *                    (needs hit_ids)
+ *   counters (R x 4) work counters, optional: BVH nodes visited, surfels
+ *                    tested, k-buffer insertions, rounds
  * A ray with a non-finite component or a zero direction gets O = 0, F = 0,
  * D = 0, T = 1, n_hits = 0. */
 typedef struct {
@@ -112,6 +114,7 @@ typedef struct {
     int32_t* hit_ids;
     float* hit_T;
     int32_t H_cap;
+    int32_t* counters;
 } irgs_out;
 
 /* Upstream gradients dL/dO (R), dL/dF (R x F), dL/dD (R); any may be NULL

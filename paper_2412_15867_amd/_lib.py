@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
 
 class Out(ctypes.Structure):
     _fields_ = [("opacity", c_vp), ("feat", c_vp), ("depth", c_vp), ("T", c_vp), ("n_hits", c_vp),
-                ("hit_ids", c_vp), ("hit_T", c_vp), ("H_cap", c_i32)]
+                ("hit_ids", c_vp), ("hit_T", c_vp), ("H_cap", c_i32), ("counters", c_vp)]
 
 
 class GradIn(ctypes.Structure):

@@ -144,6 +144,7 @@ OutPtrs out_ptrs(const irgs_out* o)
     r.hit_ids = o->hit_ids;
     r.hit_T = o->hit_ids ? o->hit_T : nullptr;
     r.H_cap = o->hit_ids ? o->H_cap : 0;
+    r.counters = o->counters;
     return r;
 }
 

@@ -41,6 +41,7 @@ struct OutPtrs {
     int32_t* hit_ids;
     float* hit_T;
     int32_t H_cap;
+    int32_t* counters;  // optional R x 4 work counters
 };
 
 struct GradIn {

@@ -15,6 +15,11 @@
 
 namespace irgs {
 
+// Work counters of one ray (kept in registers, written only on request).
+struct Counters {
+    int nodes = 0, tests = 0, inserts = 0, rounds = 0;
+};
+
 template <int K>
 struct KBuf {
     float t[K];
@@ -60,14 +65,16 @@ struct KBuf {
 // K-th-key cut once full.
 template <int K>
 __device__ __forceinline__ void offer(KBuf<K>& kb, const SurfelRec& s, const Ray& ray, float t_min, float t_max,
-                                      float last_t, int last_i)
+                                      float last_t, int last_i, Counters& ct)
 {
+    ++ct.tests;
     float tau, rho2;
     if (!hit_test(s, ray, t_min, t_max, &tau, &rho2)) return;
     const int id = __float_as_int(s.c.w);
     if (!key_less(last_t, last_i, tau, id)) return;
     if (!key_less(tau, id, kb.t[K - 1], kb.id[K - 1])) return;
     const float alpha = s.a.w * __expf(-0.5f * rho2);
+    ++ct.inserts;
     kb.insert(tau, id, alpha);
 }
 
@@ -100,13 +107,16 @@ struct Stack {
 // window [max(t_min, last_t), min(t_max, K-th key)], nearer child first.
 template <int K>
 __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, const Ray& ray, float ix, float iy,
-                                            float iz, float t_min, float t_max, float last_t, int last_i, Stack& st)
+                                            float iz, float t_min, float t_max, float last_t, int last_i, Stack& st,
+                                            Counters& ct)
 {
+    ++ct.rounds;
     const float lo = fmaxf(t_min, last_t);
     const float tmax_c = fminf(t_max, 3.0e38f);
     st.sp = 0;
     int node = 0;
     while (true) {
+        ++ct.nodes;
         const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
         const float4 p0 = np[0], p1 = np[1], p2 = np[2];
         const int4 ch = reinterpret_cast<const int4*>(np)[3];
@@ -117,11 +127,11 @@ __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, co
         bool h1 = ch.y != kNoChild &&
                   box_hit(p1.z, p1.w, p2.x, p2.y, p2.z, p2.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te1);
         if (h0 && (ch.x & kLeafBit)) {
-            offer<K>(kb, load_rec(sc.rec, ch.x & ~kLeafBit), ray, t_min, t_max, last_t, last_i);
+            offer<K>(kb, load_rec(sc.rec, ch.x & ~kLeafBit), ray, t_min, t_max, last_t, last_i, ct);
             h0 = false;
         }
         if (h1 && (ch.y & kLeafBit)) {
-            offer<K>(kb, load_rec(sc.rec, ch.y & ~kLeafBit), ray, t_min, t_max, last_t, last_i);
+            offer<K>(kb, load_rec(sc.rec, ch.y & ~kLeafBit), ray, t_min, t_max, last_t, last_i, ct);
             h1 = false;
         }
         if (h0 && h1) {
@@ -143,9 +153,10 @@ __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, co
 // The record index is uniform across the wave, so loads are broadcast.
 template <int K>
 __device__ __forceinline__ void collect_all(KBuf<K>& kb, const SceneView& sc, const Ray& ray, float t_min,
-                                            float t_max, float last_t, int last_i)
+                                            float t_max, float last_t, int last_i, Counters& ct)
 {
-    for (int i = 0; i < sc.n; ++i) offer<K>(kb, load_rec(sc.rec, i), ray, t_min, t_max, last_t, last_i);
+    ++ct.rounds;
+    for (int i = 0; i < sc.n; ++i) offer<K>(kb, load_rec(sc.rec, i), ray, t_min, t_max, last_t, last_i, ct);
 }
 
 __device__ __forceinline__ bool ray_valid(const Ray& r)

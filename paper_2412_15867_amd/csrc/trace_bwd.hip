@@ -156,6 +156,7 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
         return;
     }
     // ---- re-march: pass 1 records the state at the start of each round
+    Counters ct;
     const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
     float last_t = -__int_as_float(0x7f800000);
     int last_i = -1;
@@ -168,7 +169,7 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
             ck[rounds * ck_stride] = make_float4(last_t, __int_as_float(last_i), T, __int_as_float(nh));
         KBuf<K> kb;
         kb.clear();
-        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st);
+        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < kb.cnt && !done) {
@@ -197,7 +198,7 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
         KBuf<K> kb;
         for (int adv = base; adv < rr; ++adv) {  // rounds past the last checkpoint
             kb.clear();
-            collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st);
+            collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
 #pragma unroll
             for (int j = 0; j < K; ++j) T = j < kb.cnt ? T * (1.0f - kb.a[j]) : T;
             nb += kb.cnt;
@@ -205,7 +206,7 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
             last_i = kb.id[K - 1];
         }
         kb.clear();
-        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st);
+        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
         const int m = min(kb.cnt, total - nb);
         float Tj[K];
 #pragma unroll

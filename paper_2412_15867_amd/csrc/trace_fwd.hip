@@ -34,6 +34,7 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
 #pragma unroll
     for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
     int nh = 0;
+    Counters ct;
     if (sc.n > 0 && ray_valid(ray)) {
         const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
         float last_t = -__int_as_float(0x7f800000);
@@ -43,9 +44,9 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
             KBuf<K> kb;
             kb.clear();
             if (BVH)
-                collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st);
+                collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
             else
-                collect_all<K>(kb, sc, ray, P.t_min, P.t_max, last_t, last_i);
+                collect_all<K>(kb, sc, ray, P.t_min, P.t_max, last_t, last_i, ct);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (j < kb.cnt && !done) {
@@ -82,6 +83,8 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
         if (c < P.F) out.feat[r * P.F + c] = acc[c];
     if (out.T) out.T[r] = T;
     if (out.n_hits) out.n_hits[r] = nh;
+    if (out.counters)
+        reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
 }
 
 template <int K, int FM, bool BVH>

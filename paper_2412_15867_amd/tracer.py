@@ -165,6 +165,7 @@ class TraceResult:
     n_hits: Optional[torch.Tensor] = None
     hit_ids: Optional[torch.Tensor] = None
     hit_T: Optional[torch.Tensor] = None
+    counters: Optional[torch.Tensor] = None   # (R, 4): nodes, tests, inserts, rounds
 
     def out_struct(self) -> _lib.Out:
         H = 0 if self.hit_ids is None else int(self.hit_ids.shape[1])
@@ -172,18 +173,22 @@ class TraceResult:
                         None if self.T is None else self.T.data_ptr(),
                         None if self.n_hits is None else self.n_hits.data_ptr(),
                         None if self.hit_ids is None else self.hit_ids.data_ptr(),
-                        None if self.hit_T is None else self.hit_T.data_ptr(), H)
+                        None if self.hit_T is None else self.hit_T.data_ptr(), H,
+                        None if self.counters is None else self.counters.data_ptr())
 
 
 def alloc_result(R: int, F: int, device, hit_cap: int = 0, with_T: bool = True, with_n: bool = True,
-                 with_hit_T: bool = True) -> TraceResult:
+                 with_hit_T: bool = True, counters: bool = False) -> TraceResult:
     f32 = dict(dtype=torch.float32, device=device)
-    return TraceResult(
+    res = TraceResult(
         torch.empty(R, **f32), torch.empty((R, F), **f32), torch.empty(R, **f32),
         torch.empty(R, **f32) if with_T else None,
         torch.empty(R, dtype=torch.int32, device=device) if with_n else None,
         torch.empty((R, hit_cap), dtype=torch.int32, device=device) if hit_cap > 0 else None,
         torch.empty((R, hit_cap), **f32) if (hit_cap > 0 and with_hit_T) else None)
+    if counters:
+        res.counters = torch.empty((R, 4), dtype=torch.int32, device=device)
+    return res
 
 
 def _rays(scene: Scene, ro: torch.Tensor, rd: torch.Tensor):
@@ -194,14 +199,14 @@ def _rays(scene: Scene, ro: torch.Tensor, rd: torch.Tensor):
 
 
 def trace(scene: Scene, ro: torch.Tensor, rd: torch.Tensor, cfg: Optional[TraceConfig] = None,
-          hit_cap: int = 0, out: Optional[TraceResult] = None, **kw) -> TraceResult:
+          hit_cap: int = 0, out: Optional[TraceResult] = None, counters: bool = False, **kw) -> TraceResult:
     """Forward trace of the rays (ro, rd), each (R, 3) float32 on the scene's
     device.  Returns opacity O (R), blended features (R, F), unnormalised
     depth (R), final transmittance T, n_hits and, with hit_cap > 0, the first
     hit_cap hit ids and the transmittance before each."""
     cfg = cfg or TraceConfig(**kw)
     R = _rays(scene, ro, rd)
-    res = out or alloc_result(R, scene.F, scene.device, hit_cap)
+    res = out or alloc_result(R, scene.F, scene.device, hit_cap, counters=counters)
     flags = _lib.FLAG_BRUTE_FORCE if cfg.brute_force else 0
     p = scene.params(cfg, flags)
     o = res.out_struct()

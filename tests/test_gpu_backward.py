@@ -133,6 +133,15 @@ def test_finite_differences_on_surface_patch():
     validate(sub.astuple(), ro, rd, fwd)
     ref = ograd.grad_given_hits(sub.astuple(), ro, rd, lists_of(fwd), gO, gF, gD)
     grad_close(a, ref)
+    # Finite differences see the oracle's own hit lists; keep the rays on
+    # which the GPU list is the same, and differentiate those on both sides.
+    orc = oracle.trace(sub.astuple(), ro, rd, hit_cap=256)
+    same = np.array([fwd["n_hits"][r] == orc["n_hits"][r] and
+                     np.array_equal(fwd["hit_ids"][r, :fwd["n_hits"][r]], orc["hits"][r, :orc["n_hits"][r]])
+                     for r in range(ro.shape[0])])
+    assert same.mean() > 0.5
+    ro, rd, gO, gF, gD = ro[same], rd[same], gO[same], gF[same], gD[same]
+    fwd, a = gpu_fwd_bwd(sub.astuple(), ro, rd, gO, gF, gD, hit_cap=256)
     # finite differences on the first 48 surfels (every parameter of each)
     keep = np.arange(48)
     surf = [np.array(x, dtype=np.float64) for x in sub.astuple()]
