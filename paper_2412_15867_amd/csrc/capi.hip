@@ -31,6 +31,12 @@ struct irgs_scene_s {
     float* leafbox = nullptr;
     uint32_t* counters = nullptr;
     int* depth = nullptr;
+    int2* brange = nullptr;
+    WideNode* wnodes = nullptr;
+    int4* wsrc = nullptr;
+    int* wscratch = nullptr;
+    int n_wide = 0;
+    int wide_depth = 0;
 };
 
 namespace {
@@ -72,6 +78,14 @@ void free_scene_buffers(irgs_scene s)
     hipFree(s->leafbox);
     hipFree(s->counters);
     hipFree(s->depth);
+    hipFree(s->brange);
+    hipFree(s->wnodes);
+    hipFree(s->wsrc);
+    hipFree(s->wscratch);
+    s->brange = nullptr;
+    s->wnodes = nullptr;
+    s->wsrc = nullptr;
+    s->wscratch = nullptr;
     s->rec = nullptr;
     s->nodes = nullptr;
     s->leaf_parent = nullptr;
@@ -113,6 +127,12 @@ BuildArgs build_args(irgs_scene s)
     a.leaf_parent = s->leaf_parent;
     a.counters = s->counters;
     a.depth = s->depth;
+    a.brange = s->brange;
+    a.wnodes = s->wnodes;
+    a.wsrc = s->wsrc;
+    a.wscratch = s->wscratch;
+    a.n_wide = s->n_wide;
+    a.wide_depth = s->wide_depth;
     return a;
 }
 
@@ -120,16 +140,20 @@ SceneView view_of(irgs_scene s)
 {
     SceneView v{};
     v.rec = s->rec;
-    v.nodes = s->nodes;
+    v.wnodes = s->wnodes;
     v.feat = s->p.feat;
     v.n = static_cast<int32_t>(s->n);
     v.F = s->F;
     return v;
 }
 
+// Entries a traversal stack can hold at most: every wide level above the
+// current node pushes at most 3 siblings.
+int stack_need(irgs_scene s) { return 3 * s->wide_depth + 1; }
+
 int ovf_slots_of(irgs_scene s)
 {
-    const int extra = s->max_depth - kStackLds + 1;
+    const int extra = stack_need(s) - kStackLds;
     return extra > 0 ? extra : 0;
 }
 
@@ -218,7 +242,9 @@ size_t irgs_scene_bytes(int64_t n, int32_t F)
     lbvh_sort_scratch_bytes(static_cast<int>(n), &sort);
     const size_t ni = static_cast<size_t>(n_internal(n));
     return static_cast<size_t>(n) * (sizeof(SurfelRec) + sizeof(int) + sizeof(uint32_t) + 6 * sizeof(float)) +
-           ni * (sizeof(BvhNode) + sizeof(uint32_t)) + sizeof(int) + sort;
+           ni * (sizeof(BvhNode) + sizeof(uint32_t) + sizeof(int2) + sizeof(WideNode) + sizeof(int4) +
+                 3 * sizeof(int)) +
+           sizeof(int) * 5 + sort;
 }
 
 size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
@@ -271,7 +297,10 @@ irgs_status irgs_scene_build(irgs_scene s, const irgs_params* p, void* stream)
         if ((e = dalloc(&s->rec, n)) != hipSuccess || (e = dalloc(&s->nodes, n_internal(n))) != hipSuccess ||
             (e = dalloc(&s->leaf_parent, n)) != hipSuccess || (e = dalloc(&s->order, n)) != hipSuccess ||
             (e = dalloc(&s->leafbox, 6 * n)) != hipSuccess || (e = dalloc(&s->counters, n_internal(n))) != hipSuccess ||
-            (e = dalloc(&s->depth, 1)) != hipSuccess) {
+            (e = dalloc(&s->depth, 1)) != hipSuccess || (e = dalloc(&s->brange, n_internal(n))) != hipSuccess ||
+            (e = dalloc(&s->wnodes, n_internal(n))) != hipSuccess ||
+            (e = dalloc(&s->wsrc, n_internal(n))) != hipSuccess ||
+            (e = dalloc(&s->wscratch, 3 * n_internal(n) + 4)) != hipSuccess) {
             free_scene_buffers(s);
             return hip_fail(e, "scene allocation");
         }
@@ -288,7 +317,10 @@ irgs_status irgs_scene_build(irgs_scene s, const irgs_params* p, void* stream)
     lbvh_sort_scratch_bytes(static_cast<int>(n), &sort_bytes);
     void* scratch = nullptr;
     if ((e = hipMalloc(&scratch, sort_bytes)) != hipSuccess) return hip_fail(e, "build scratch");
-    e = lbvh_build(build_args(s), scratch, st);
+    BuildArgs ba = build_args(s);
+    e = lbvh_build(ba, scratch, st);
+    s->n_wide = ba.n_wide;
+    s->wide_depth = ba.wide_depth;
     int depth = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&depth, s->depth, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -340,7 +372,7 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
     if (R == 0 || s->n == 0) return IRGS_OK;
     const bool use_saved = !(p->flags & IRGS_FLAG_RECOMPUTE) && saved->hit_ids && saved->hit_T && saved->H_cap > 0;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const int slots = ovf_slots_of(s);
+    const int slots = stack_need(s);  // the backward keeps its whole re-march stack in global memory
     const size_t thr = static_cast<size_t>(trace_threads(R));
     AsyncBuf ovf, ck;
     hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);

@@ -44,19 +44,32 @@ struct __align__(16) BvhNode {
     int4 ch;    // child0, child1, parent, unused
 };
 
-struct Box {
-    float lo[3], hi[3];
+// 4-wide node used by the traversal (collapsed from the binary tree), child
+// boxes stored per axis so the four slab tests share instructions.  A child
+// reference r >= 0 is a wide node; r with kLeafBit set is a cluster of
+// ((r & 15) + 1) surfels starting at Morton position ((r & ~kLeafBit) >> 4);
+// kNoChild is an empty slot (its box is all +inf).
+struct __align__(16) WideNode {
+    float4 lo_x, lo_y, lo_z;
+    float4 hi_x, hi_y, hi_z;
+    int4 child;
+    int4 meta;  // unused
 };
+
+constexpr int kLeafMax = 4;  // surfels per cluster leaf (at most 16)
+
+__host__ __device__ __forceinline__ int cluster_ref(int first, int count)
+{
+    return kLeafBit | (first << 4) | (count - 1);
+}
 
 // What a trace kernel needs of one scene (passed by value).
 struct SceneView {
-    const SurfelRec* rec;  // N records, Morton order
-    const BvhNode* nodes;  // N-1 internal nodes (N == 1: one node), root = 0
-    const float* feat;     // N x F, caller layout (original ids)
+    const SurfelRec* rec;   // N records, Morton order
+    const WideNode* wnodes; // 4-wide nodes, root = 0
+    const float* feat;      // N x F, caller layout (original ids)
     int32_t n;
     int32_t F;
-    int32_t root_is_leaf;  // unused (kept for layout), root always node 0
-    int32_t pad;
 };
 
 struct TraceParams {
@@ -92,29 +105,34 @@ __device__ __forceinline__ float quat_frame(float4 q, float* tu, float* tv, floa
     return qn;
 }
 
-// Eq. 6-7 against one record.  Returns true for a hit strictly after the
-// resume key (t_last, id_last) and inside (t_min, t_max); writes tau and
-// rho2 = u^2 + v^2.  Every kernel (brute force, BVH, packed, backward
-// recompute) calls this same function, so a given (ray, surfel) pair is
-// decided and ordered identically everywhere.
-__device__ __forceinline__ bool hit_test(const SurfelRec& s, const Ray& r, float t_min, float t_max,
-                                         float* tau_out, float* rho2_out)
+// Eq. 6-7 against one record: depth tau and rho2 = u^2 + v^2 of the ray's
+// crossing of the surfel plane.  Every kernel (brute force, BVH, packed,
+// composite, backward re-march) evaluates a (ray, surfel) pair through this
+// one function, so the pair is decided and ordered identically everywhere.
+__device__ __forceinline__ void plane_hit(const SurfelRec& s, const Ray& r, float* tau_out, float* rho2_out)
 {
     const float wx = s.a.x - r.ox, wy = s.a.y - r.oy, wz = s.a.z - r.oz;
     const float den = dot3(s.b.x, s.b.y, s.b.z, r.dx, r.dy, r.dz);
     const float num = dot3(s.b.x, s.b.y, s.b.z, wx, wy, wz);
     const float tau = num / den;
-    // den == 0 gives +-inf or NaN, both rejected by the window test.
-    if (!(tau > t_min && tau < t_max)) return false;
     const float px = fmaf(tau, r.dx, -wx), py = fmaf(tau, r.dy, -wy), pz = fmaf(tau, r.dz, -wz);
     const float u = dot3(px, py, pz, s.c.x, s.c.y, s.c.z);
     const float v = dot3(px, py, pz, s.d.x, s.d.y, s.d.z);
-    const float rho2 = fmaf(u, u, v * v);
-    if (!(rho2 <= s.b.w)) return false;
     *tau_out = tau;
-    *rho2_out = rho2;
-    return true;
+    *rho2_out = fmaf(u, u, v * v);
 }
+
+// A hit: inside (t_min, t_max) (n.r_d == 0 gives +-inf or NaN, rejected) and
+// inside the support rho2 <= rho2_max.
+__device__ __forceinline__ bool hit_test(const SurfelRec& s, const Ray& r, float t_min, float t_max,
+                                         float* tau_out, float* rho2_out)
+{
+    plane_hit(s, r, tau_out, rho2_out);
+    return (*tau_out > t_min && *tau_out < t_max) && (*rho2_out <= s.b.w);
+}
+
+// alpha = o exp(-rho2 / 2) (Eq. 7 times the opacity).
+__device__ __forceinline__ float alpha_of(const SurfelRec& s, float rho2) { return s.a.w * __expf(-0.5f * rho2); }
 
 __device__ __forceinline__ SurfelRec load_rec(const SurfelRec* __restrict__ rec, int i)
 {

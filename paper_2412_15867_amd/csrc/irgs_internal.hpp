@@ -26,10 +26,17 @@ struct BuildArgs {
     int* leaf_parent;
     uint32_t* counters;
     int* depth;             // device int: max number of internal ancestors of a leaf
+    int2* brange;           // per binary node: first leaf, leaf count
+    WideNode* wnodes;       // up to max(N - 1, 1) wide nodes
+    int4* wsrc;             // per wide node and slot: (binary parent << 1 | side), -1 = empty
+    int* wscratch;          // 2 * max(N - 1, 1) + 4 ints: frontiers and counters
+    int n_wide;             // out (host): wide nodes built; also the refit input
+    int wide_depth;         // out (host): levels of the wide tree
 };
 
 hipError_t lbvh_sort_scratch_bytes(int n, size_t* bytes);
-hipError_t lbvh_build(const BuildArgs& a, void* scratch, hipStream_t st);
+// Build: synchronises `st` (the wide collapse reads each level's size back).
+hipError_t lbvh_build(BuildArgs& a, void* scratch, hipStream_t st);
 hipError_t lbvh_refit(const BuildArgs& a, hipStream_t st);
 
 struct OutPtrs {

@@ -295,7 +295,7 @@ __device__ __forceinline__ int lcp(const uint64_t* __restrict__ keys, int n, int
 }
 
 __global__ void k_karras(int n, const uint64_t* __restrict__ keys, BvhNode* __restrict__ nodes,
-                         int* __restrict__ leaf_parent)
+                         int* __restrict__ leaf_parent, int2* __restrict__ brange)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
@@ -316,6 +316,7 @@ __global__ void k_karras(int n, const uint64_t* __restrict__ keys, BvhNode* __re
     } while (t > 1);
     const int g = i + s * d + min(d, 0);
     const int lo = min(i, j), hi = max(i, j);
+    brange[i] = make_int2(lo, hi - lo + 1);
     const int left = (lo == g) ? (g | kLeafBit) : g;
     const int right = (hi == g + 1) ? ((g + 1) | kLeafBit) : (g + 1);
     nodes[i].ch.x = left;
@@ -331,9 +332,10 @@ __global__ void k_karras(int n, const uint64_t* __restrict__ keys, BvhNode* __re
     if (i == 0) nodes[0].ch.z = -1;
 }
 
-__global__ void k_single_root(BvhNode* nodes, int* leaf_parent)
+__global__ void k_single_root(BvhNode* nodes, int* leaf_parent, int2* brange)
 {
     const float inf = __int_as_float(0x7f800000);
+    brange[0] = make_int2(0, 1);
     nodes[0].ch = make_int4(0 | kLeafBit, kNoChild, -1, 0);
     nodes[0].p1.z = inf, nodes[0].p1.w = inf;
     nodes[0].p2 = make_float4(inf, inf, inf, inf);
@@ -435,6 +437,116 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
         p[i] = v;
 }
 
+// ---------------------------------------------------------------- wide tree
+__device__ __forceinline__ float box_area(const float* b)
+{
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__device__ __forceinline__ void set_wide_box(WideNode* w, int slot, const float* b)
+{
+    float* f = reinterpret_cast<float*>(w);
+    for (int k = 0; k < 6; ++k) f[k * 4 + slot] = b[k];
+}
+
+// One level of the top-down collapse: wide node w stands for binary node b;
+// its up-to-four children are found by repeatedly opening the candidate with
+// the largest box area, as long as that candidate holds more than kLeafMax
+// surfels.  Candidates with at most kLeafMax surfels become cluster leaves
+// (their surfels are contiguous in Morton order); larger ones become new wide
+// nodes of the next level.
+__global__ void k_collapse(int nfront, const int* __restrict__ front_in, int* __restrict__ front_out,
+                           int* __restrict__ counts, int* __restrict__ wide_src, const BvhNode* __restrict__ bn,
+                           const int2* __restrict__ brange, WideNode* __restrict__ wn, int4* __restrict__ wsrc)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nfront) return;
+    const int w = front_in[t];
+    const int b = wide_src[w];
+    int ref[4], par[4], side[4];
+    float area[4];
+    int m = 0;
+    auto add = [&](int p, int sd) {
+        const int r = sd == 0 ? bn[p].ch.x : bn[p].ch.y;
+        if (r == kNoChild) return;
+        float bx[6];
+        child_box(bn[p], sd, bx);
+        ref[m] = r, par[m] = p, side[m] = sd, area[m] = box_area(bx);
+        ++m;
+    };
+    add(b, 0);
+    add(b, 1);
+    while (m < 4) {
+        int best = -1;
+        float ba = -1.0f;
+        for (int c = 0; c < m; ++c) {
+            const bool internal = (ref[c] & kLeafBit) == 0;
+            if (internal && brange[ref[c]].y > kLeafMax && area[c] > ba) {
+                best = c;
+                ba = area[c];
+            }
+        }
+        if (best < 0) break;
+        const int open = ref[best];
+        // replace `best` by its first child, append the second
+        const int r0 = bn[open].ch.x, r1 = bn[open].ch.y;
+        float bx[6];
+        child_box(bn[open], 0, bx);
+        ref[best] = r0, par[best] = open, side[best] = 0, area[best] = box_area(bx);
+        child_box(bn[open], 1, bx);
+        ref[m] = r1, par[m] = open, side[m] = 1, area[m] = box_area(bx);
+        ++m;
+    }
+    WideNode node;
+    int4 src = make_int4(-1, -1, -1, -1);
+    int* srcp = reinterpret_cast<int*>(&src);
+    int* chp = reinterpret_cast<int*>(&node.child);
+    const float inf = __int_as_float(0x7f800000);
+    const float empty[6] = {inf, inf, inf, inf, inf, inf};
+    for (int c = 0; c < 4; ++c) {
+        if (c >= m) {
+            set_wide_box(&node, c, empty);
+            chp[c] = kNoChild;
+            continue;
+        }
+        float bx[6];
+        child_box(bn[par[c]], side[c], bx);
+        set_wide_box(&node, c, bx);
+        srcp[c] = (par[c] << 1) | side[c];
+        const int r = ref[c];
+        if (r & kLeafBit) {
+            chp[c] = cluster_ref(r & ~kLeafBit, 1);
+        } else if (brange[r].y <= kLeafMax) {
+            chp[c] = cluster_ref(brange[r].x, brange[r].y);
+        } else {
+            const int nw = atomicAdd(&counts[0], 1);
+            wide_src[nw] = r;
+            front_out[atomicAdd(&counts[1], 1)] = nw;
+            chp[c] = nw;
+        }
+    }
+    node.meta = make_int4(0, 0, 0, 0);
+    wn[w] = node;
+    wsrc[w] = src;
+}
+
+// Wide boxes from the (refit) binary boxes they were taken from.
+__global__ void k_wide_refit(int nw, const int4* __restrict__ wsrc, const BvhNode* __restrict__ bn,
+                             WideNode* __restrict__ wn)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nw) return;
+    const int4 s4 = wsrc[w];
+    const int sv[4] = {s4.x, s4.y, s4.z, s4.w};
+    for (int c = 0; c < 4; ++c) {
+        if (sv[c] < 0) continue;
+        float bx[6];
+        child_box(bn[sv[c] >> 1], sv[c] & 1, bx);
+        set_wide_box(&wn[w], c, bx);
+    }
+}
+
 inline int blocks_for(int64_t n, int t) { return static_cast<int>((n + t - 1) / t); }
 
 
@@ -458,6 +570,14 @@ hipError_t lbvh_sort_scratch_bytes(int n, size_t* bytes)
     return hipSuccess;
 }
 
+__global__ void k_collapse_init(int* wide_src, int* front, int* counts)
+{
+    wide_src[0] = 0;
+    front[0] = 0;
+    counts[0] = 1;
+    counts[1] = 0;
+}
+
 // Records + leaf boxes in the current leaf order, then bottom-up boxes.
 static hipError_t refit_boxes(const BuildArgs& a, hipStream_t st)
 {
@@ -473,7 +593,7 @@ static hipError_t refit_boxes(const BuildArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t lbvh_build(const BuildArgs& a, void* scratch, hipStream_t st)
+hipError_t lbvh_build(BuildArgs& a, void* scratch, hipStream_t st)
 {
     const int n = a.n;
     if (n <= 0) return hipSuccess;
@@ -523,14 +643,44 @@ hipError_t lbvh_build(const BuildArgs& a, void* scratch, hipStream_t st)
     e = fill_u32(a.nodes, static_cast<int64_t>(nint) * (sizeof(BvhNode) / 4), 0u, st);
     if (e != hipSuccess) return e;
     if (n == 1) {
-        k_single_root<<<1, 1, 0, st>>>(a.nodes, a.leaf_parent);
+        k_single_root<<<1, 1, 0, st>>>(a.nodes, a.leaf_parent, a.brange);
     } else {
-        k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(n, k0, a.nodes, a.leaf_parent);
+        k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(n, k0, a.nodes, a.leaf_parent, a.brange);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = refit_boxes(a, st);
     if (e != hipSuccess) return e;
+    // top-down collapse into the 4-wide tree, one level per launch
+    {
+        const int nmax = nint;
+        int* wide_src = a.wscratch;
+        int* fa = a.wscratch + nmax;
+        int* fb = a.wscratch + 2 * nmax;
+        int* counts = a.wscratch + 3 * nmax;
+        k_collapse_init<<<1, 1, 0, st>>>(wide_src, fa, counts);
+        int nfront = 1, levels = 0;
+        while (nfront > 0) {
+            e = fill_u32(counts + 1, 1, 0u, st);
+            if (e != hipSuccess) return e;
+            k_collapse<<<blocks_for(nfront, 128), 128, 0, st>>>(nfront, fa, fb, counts, wide_src, a.nodes,
+                                                                  a.brange, a.wnodes, a.wsrc);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(&nfront, counts + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return e;
+            int* t = fa;
+            fa = fb;
+            fb = t;
+            ++levels;
+        }
+        int nw = 0;
+        e = hipMemcpyAsync(&nw, counts, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        a.n_wide = nw;
+        a.wide_depth = levels;
+    }
     e = fill_u32(a.depth, 1, 0u, st);
     if (e != hipSuccess) return e;
     k_depth<<<blocks_for(n, 256), 256, 0, st>>>(n, a.leaf_parent, a.nodes, a.depth);
@@ -540,7 +690,10 @@ hipError_t lbvh_build(const BuildArgs& a, void* scratch, hipStream_t st)
 hipError_t lbvh_refit(const BuildArgs& a, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
-    return refit_boxes(a, st);
+    hipError_t e = refit_boxes(a, st);
+    if (e != hipSuccess) return e;
+    k_wide_refit<<<blocks_for(a.n_wide, 256), 256, 0, st>>>(a.n_wide, a.wsrc, a.nodes, a.wnodes);
+    return hipGetLastError();
 }
 
 }  // namespace irgs

@@ -20,11 +20,13 @@ struct Counters {
     int nodes = 0, tests = 0, inserts = 0, rounds = 0;
 };
 
+// The k-buffer holds (tau, Morton position) keys, ascending.  Equal depths
+// are ordered by Morton position, which every kernel shares.  alpha and the
+// surfel id are re-read from the record when the entry is composited.
 template <int K>
 struct KBuf {
     float t[K];
     int id[K];
-    float a[K];
     int cnt;
 
     __device__ __forceinline__ void clear()
@@ -33,78 +35,74 @@ struct KBuf {
         for (int j = 0; j < K; ++j) {
             t[j] = __int_as_float(0x7f800000);  // +inf
             id[j] = 0x7fffffff;
-            a[j] = 0.0f;
         }
         cnt = 0;
     }
 
-    // Far bound of the current round: the K-th key once the buffer is full.
     __device__ __forceinline__ bool full() const { return cnt >= K; }
 
-    // Insert (tt, ii, aa); the largest key falls off the end when full.
-    __device__ __forceinline__ void insert(float tt, int ii, float aa)
+    // Insert (tt, ii); the largest key falls off the end when full.
+    __device__ __forceinline__ void insert(float tt, int ii)
     {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const bool lt = key_less(tt, ii, t[j], id[j]);
             const float t2 = lt ? t[j] : tt;
             const int i2 = lt ? id[j] : ii;
-            const float a2 = lt ? a[j] : aa;
             t[j] = lt ? tt : t[j];
             id[j] = lt ? ii : id[j];
-            a[j] = lt ? aa : a[j];
             tt = t2;
             ii = i2;
-            aa = a2;
         }
         cnt = cnt < K ? cnt + 1 : K;
     }
 };
 
-// Offer one record to the buffer: Eq. 6-7 test, resume-key window, and the
-// K-th-key cut once full.
+// Offer the record at Morton position `pos` to the buffer: Eq. 6-7 test,
+// resume-key window, and the K-th-key cut once full.
 template <int K>
-__device__ __forceinline__ void offer(KBuf<K>& kb, const SurfelRec& s, const Ray& ray, float t_min, float t_max,
-                                      float last_t, int last_i, Counters& ct)
+__device__ __forceinline__ void offer(KBuf<K>& kb, const SurfelRec& s, int pos, const Ray& ray, float t_min,
+                                      float t_max, float last_t, int last_i, Counters& ct)
 {
     ++ct.tests;
     float tau, rho2;
     if (!hit_test(s, ray, t_min, t_max, &tau, &rho2)) return;
-    const int id = __float_as_int(s.c.w);
-    if (!key_less(last_t, last_i, tau, id)) return;
-    if (!key_less(tau, id, kb.t[K - 1], kb.id[K - 1])) return;
-    const float alpha = s.a.w * __expf(-0.5f * rho2);
+    if (!key_less(last_t, last_i, tau, pos)) return;
+    if (!key_less(tau, pos, kb.t[K - 1], kb.id[K - 1])) return;
     ++ct.inserts;
-    kb.insert(tau, id, alpha);
+    kb.insert(tau, pos);
 }
 
-// Per-lane traversal stack: the first kStackLds entries live in LDS
+// Per-lane traversal stack: the first `lds_slots` entries live in LDS
 // (slot-major, so a wave's pushes hit distinct banks), deeper entries in a
 // global overflow area sized from the tree depth at build time.
 struct Stack {
-    int* lds;       // this block's LDS stack base: [kStackLds][kBlock]
+    int* lds;       // this block's LDS stack base: [lds_slots][kBlock]
     int* ovf;       // global overflow base for slot 0 of this thread
     int ovf_stride; // distance between overflow slots
     int tid;        // thread index within the block
     int sp;
+    int lds_slots;
 
     __device__ __forceinline__ void push(int v)
     {
-        if (sp < kStackLds)
+        if (sp < lds_slots)
             lds[sp * kBlock + tid] = v;
         else
-            ovf[(sp - kStackLds) * ovf_stride] = v;
+            ovf[(sp - lds_slots) * ovf_stride] = v;
         ++sp;
     }
     __device__ __forceinline__ int pop()
     {
         --sp;
-        return sp < kStackLds ? lds[sp * kBlock + tid] : ovf[(sp - kStackLds) * ovf_stride];
+        return sp < lds_slots ? lds[sp * kBlock + tid] : ovf[(sp - lds_slots) * ovf_stride];
     }
 };
 
-// One round of collection by BVH traversal.  Boxes are culled against the
-// window [max(t_min, last_t), min(t_max, K-th key)], nearer child first.
+// One round of collection by traversal of the 4-wide tree.  Child boxes
+// are culled against the window [max(t_min, last_t), min(t_max, K-th key)];
+// cluster leaves are tested on the spot, inner children are visited nearest
+// first (the others are pushed farthest first).
 template <int K>
 __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, const Ray& ray, float ix, float iy,
                                             float iz, float t_min, float t_max, float last_t, int last_i, Stack& st,
@@ -113,35 +111,62 @@ __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, co
     ++ct.rounds;
     const float lo = fmaxf(t_min, last_t);
     const float tmax_c = fminf(t_max, 3.0e38f);
+    const float inf = __int_as_float(0x7f800000);
     st.sp = 0;
     int node = 0;
     while (true) {
         ++ct.nodes;
-        const float4* np = reinterpret_cast<const float4*>(sc.nodes + node);
-        const float4 p0 = np[0], p1 = np[1], p2 = np[2];
-        const int4 ch = reinterpret_cast<const int4*>(np)[3];
+        const float4* np = reinterpret_cast<const float4*>(sc.wnodes + node);
+        const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5];
+        const int4 ch = reinterpret_cast<const int4*>(np)[6];
         const float hi = kb.full() ? fminf(kb.t[K - 1], tmax_c) : tmax_c;
-        float te0, te1;
-        bool h0 = ch.x != kNoChild &&
-                  box_hit(p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te0);
-        bool h1 = ch.y != kNoChild &&
-                  box_hit(p1.z, p1.w, p2.x, p2.y, p2.z, p2.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te1);
-        if (h0 && (ch.x & kLeafBit)) {
-            offer<K>(kb, load_rec(sc.rec, ch.x & ~kLeafBit), ray, t_min, t_max, last_t, last_i, ct);
-            h0 = false;
+        float te[4];
+        bool h[4];
+        h[0] = box_hit(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[0]);
+        h[1] = box_hit(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[1]);
+        h[2] = box_hit(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[2]);
+        h[3] = box_hit(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[3]);
+        const int c4[4] = {ch.x, ch.y, ch.z, ch.w};
+        float key[4];
+        int ref[4];
+        int leaves = 0;  // bit c: cluster child c was hit
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bool leaf = c4[c] < 0;  // cluster (kNoChild never passes the box test)
+            leaves |= (h[c] && leaf) ? (1 << c) : 0;
+            key[c] = (h[c] && !leaf) ? te[c] : inf;
+            ref[c] = c4[c];
         }
-        if (h1 && (ch.y & kLeafBit)) {
-            offer<K>(kb, load_rec(sc.rec, ch.y & ~kLeafBit), ray, t_min, t_max, last_t, last_i, ct);
-            h1 = false;
+        while (leaves) {
+            const int c = __ffs(leaves) - 1;
+            leaves &= leaves - 1;
+            const int r = c == 0 ? ch.x : (c == 1 ? ch.y : (c == 2 ? ch.z : ch.w));
+            const int first = (r & ~kLeafBit) >> 4;
+            const int cnt = (r & 15) + 1;
+            for (int q = first; q < first + cnt; ++q)
+                offer<K>(kb, load_rec(sc.rec, q), q, ray, t_min, t_max, last_t, last_i, ct);
         }
-        if (h0 && h1) {
-            const bool first0 = te0 <= te1;
-            st.push(first0 ? ch.y : ch.x);
-            node = first0 ? ch.x : ch.y;
-        } else if (h0) {
-            node = ch.x;
-        } else if (h1) {
-            node = ch.y;
+        // sort the four (entry distance, child) pairs ascending
+#define IRGS_CSWAP(a, b)                                      \
+    if (key[b] < key[a]) {                                    \
+        const float tk = key[a];                              \
+        key[a] = key[b];                                      \
+        key[b] = tk;                                          \
+        const int tr = ref[a];                                \
+        ref[a] = ref[b];                                      \
+        ref[b] = tr;                                          \
+    }
+        IRGS_CSWAP(0, 1)
+        IRGS_CSWAP(2, 3)
+        IRGS_CSWAP(0, 2)
+        IRGS_CSWAP(1, 3)
+        IRGS_CSWAP(1, 2)
+#undef IRGS_CSWAP
+        if (key[3] < inf) st.push(ref[3]);
+        if (key[2] < inf) st.push(ref[2]);
+        if (key[1] < inf) st.push(ref[1]);
+        if (key[0] < inf) {
+            node = ref[0];
         } else {
             if (st.sp == 0) break;
             node = st.pop();
@@ -156,7 +181,7 @@ __device__ __forceinline__ void collect_all(KBuf<K>& kb, const SceneView& sc, co
                                             float t_max, float last_t, int last_i, Counters& ct)
 {
     ++ct.rounds;
-    for (int i = 0; i < sc.n; ++i) offer<K>(kb, load_rec(sc.rec, i), ray, t_min, t_max, last_t, last_i, ct);
+    for (int i = 0; i < sc.n; ++i) offer<K>(kb, load_rec(sc.rec, i), i, ray, t_min, t_max, last_t, last_i, ct);
 }
 
 __device__ __forceinline__ bool ray_valid(const Ray& r)

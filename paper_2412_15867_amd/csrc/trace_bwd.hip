@@ -25,14 +25,110 @@ namespace irgs {
 
 namespace {
 
+constexpr int kHashSlots = 512;  // per block; a power of two
+constexpr int kHashProbes = 16;
+constexpr int kLdsFeat = 8;      // feature gradients pre-reduced in LDS (the rest go straight to global)
+constexpr int kLdsComp = 10 + kLdsFeat;
+
+// Per-surfel gradient components of one hit: mu (3), raw quaternion (4),
+// scales (2), opacity (1), features (F).
+template <int FM>
+struct HitGrad {
+    float g[10 + FM];
+};
+
+// Block-local pre-reduction: rays of one surface point share most of their
+// near hits, so their per-surfel gradients are summed in an LDS hash table
+// (LDS float atomics) and written to global memory once per chunk of rays.
+// A surfel that finds no slot within kHashProbes probes goes straight to the
+// global atomics.
+struct GradAcc {
+    int* keys;     // kHashSlots, -1 = empty
+    float* vals;   // [kLdsComp][kHashSlots]
+    GradOut go;
+    int F;
+
+    __device__ __forceinline__ void global_add(int64_t i, int c, float v) const
+    {
+        if (c < 3) {
+            if (go.mu) atomicAdd(go.mu + 3 * i + c, v);
+        } else if (c < 7) {
+            if (go.quat) atomicAdd(go.quat + 4 * i + (c - 3), v);
+        } else if (c < 9) {
+            if (go.scale) atomicAdd(go.scale + 2 * i + (c - 7), v);
+        } else if (c == 9) {
+            if (go.opac) atomicAdd(go.opac + i, v);
+        } else {
+            if (go.feat) atomicAdd(go.feat + i * F + (c - 10), v);
+        }
+    }
+
+    template <int FM>
+    __device__ __forceinline__ void add(int id, const HitGrad<FM>& h) const
+    {
+        uint32_t slot = (static_cast<uint32_t>(id) * 2654435761u) >> (32 - 9);
+        int found = -1;
+        for (int p = 0; p < kHashProbes; ++p) {
+            const int k = keys[slot];
+            if (k == id) {
+                found = static_cast<int>(slot);
+                break;
+            }
+            if (k == -1) {
+                const int prev = atomicCAS(&keys[slot], -1, id);
+                if (prev == -1 || prev == id) {
+                    found = static_cast<int>(slot);
+                    break;
+                }
+            }
+            slot = (slot + 1) & (kHashSlots - 1);
+        }
+        if (found >= 0) {
+#pragma unroll
+            for (int c = 0; c < 10 + FM; ++c) {
+                if (c < 10 + F) {
+                    if (c < kLdsComp)
+                        atomicAdd(vals + c * kHashSlots + found, h.g[c]);
+                    else
+                        global_add(id, c, h.g[c]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 10 + FM; ++c)
+                if (c < 10 + F) global_add(id, c, h.g[c]);
+        }
+    }
+
+    __device__ __forceinline__ void flush(int tid) const
+    {
+        for (int slot = tid; slot < kHashSlots; slot += kBlock) {
+            const int id = keys[slot];
+            if (id < 0) continue;
+            const int nc = 10 + (F < kLdsFeat ? F : kLdsFeat);
+            for (int c = 0; c < nc; ++c) {
+                const float v = vals[c * kHashSlots + slot];
+                if (v != 0.0f) global_add(id, c, v);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void clear(int tid) const
+    {
+        for (int i = tid; i < kHashSlots; i += kBlock) keys[i] = -1;
+        for (int i = tid; i < kLdsComp * kHashSlots; i += kBlock) vals[i] = 0.0f;
+    }
+};
+
 template <int FM>
 __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, const Ray& ray, float Ti, float& S,
-                                         float gO, const float* gF, float gD, const GradOut& go)
+                                         float gO, const float* gF, float gD, const GradAcc& acc)
 {
     const int64_t i = id;
     const float mx = raw.mu[3 * i], my = raw.mu[3 * i + 1], mz = raw.mu[3 * i + 2];
-    const float4 q = make_float4(raw.quat[4 * i], raw.quat[4 * i + 1], raw.quat[4 * i + 2], raw.quat[4 * i + 3]);
-    const float su = raw.scale[2 * i], sv = raw.scale[2 * i + 1];
+    const float4 q = *reinterpret_cast<const float4*>(raw.quat + 4 * i);
+    const float2 sc = *reinterpret_cast<const float2*>(raw.scale + 2 * i);
+    const float su = sc.x, sv = sc.y;
     const float o = raw.opac[i];
     float tu[3], tv[3], nn[3];
     const float qn = quat_frame(q, tu, tv, nn);
@@ -47,64 +143,66 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, c
     const float G = __expf(-0.5f * fmaf(u, u, v * v));
     const float alpha = o * G;
 
+    HitGrad<FM> h;
     float c = fmaf(gD, tau, gO);
     const float* f = raw.feat + i * F;
-    float fv[FM];
 #pragma unroll
     for (int k = 0; k < FM; ++k) {
-        fv[k] = k < F ? f[k] : 0.0f;
-        c = fmaf(gF[k], fv[k], c);
+        const float fv = k < F ? f[k] : 0.0f;
+        c = fmaf(gF[k], fv, c);
     }
     const float wgt = Ti * alpha;
     const float dA = Ti * (c - S);
     S = fmaf(alpha, c, (1.0f - alpha) * S);
 
-    if (go.feat) {
 #pragma unroll
-        for (int k = 0; k < FM; ++k)
-            if (k < F) atomicAdd(go.feat + i * F + k, wgt * gF[k]);
-    }
-    if (go.opac) atomicAdd(go.opac + i, dA * G);
+    for (int k = 0; k < FM; ++k) h.g[10 + k] = wgt * gF[k];
+    h.g[9] = dA * G;
 
     const float gu = -dA * alpha * u;
     const float gv = -dA * alpha * v;
-    if (go.scale) {
-        atomicAdd(go.scale + 2 * i, -gu * u / su);
-        atomicAdd(go.scale + 2 * i + 1, -gv * v / sv);
-    }
+    h.g[7] = -gu * u / su;
+    h.g[8] = -gv * v / sv;
     // p - mu = tau d - w;  du/d(p-mu) = t_u / s_u
     const float gpx = gu * tu[0] / su + gv * tv[0] / sv;
     const float gpy = gu * tu[1] / su + gv * tv[1] / sv;
     const float gpz = gu * tu[2] / su + gv * tv[2] / sv;
     const float gtau = fmaf(wgt, gD, dot3(gpx, gpy, gpz, ray.dx, ray.dy, ray.dz));
     const float gt_den = gtau / den;
-    if (go.mu) {
-        atomicAdd(go.mu + 3 * i, fmaf(gt_den, nn[0], -gpx));
-        atomicAdd(go.mu + 3 * i + 1, fmaf(gt_den, nn[1], -gpy));
-        atomicAdd(go.mu + 3 * i + 2, fmaf(gt_den, nn[2], -gpz));
-    }
-    if (go.quat) {
-        // dtau/dn = -(p - mu) / den;  du/dt_u = (p - mu) / s_u
-        const float gn0 = -gt_den * px, gn1 = -gt_den * py, gn2 = -gt_den * pz;
-        const float au = gu / su, av = gv / sv;
-        const float gu0 = au * px, gu1 = au * py, gu2 = au * pz;
-        const float gv0 = av * px, gv1 = av * py, gv2 = av * pz;
-        const float inv = 1.0f / qn;
-        const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
-        // derivatives of the rotation columns with respect to (w, x, y, z)
-        const float dw = 2.0f * (z * gu1 - y * gu2 - z * gv0 + x * gv2 + y * gn0 - x * gn1);
-        const float dx = 2.0f * (y * gu1 + z * gu2 + y * gv0 - 2.0f * x * gv1 + w * gv2 + z * gn0 - w * gn1 -
-                                 2.0f * x * gn2);
-        const float dy = 2.0f * (-2.0f * y * gu0 + x * gu1 - w * gu2 + x * gv0 + z * gv2 + w * gn0 + z * gn1 -
-                                 2.0f * y * gn2);
-        const float dz = 2.0f * (-2.0f * z * gu0 + w * gu1 + x * gu2 - w * gv0 - 2.0f * z * gv1 + y * gv2 +
-                                 x * gn0 + y * gn1);
-        const float proj = w * dw + x * dx + y * dy + z * dz;
-        atomicAdd(go.quat + 4 * i, (dw - w * proj) * inv);
-        atomicAdd(go.quat + 4 * i + 1, (dx - x * proj) * inv);
-        atomicAdd(go.quat + 4 * i + 2, (dy - y * proj) * inv);
-        atomicAdd(go.quat + 4 * i + 3, (dz - z * proj) * inv);
-    }
+    h.g[0] = fmaf(gt_den, nn[0], -gpx);
+    h.g[1] = fmaf(gt_den, nn[1], -gpy);
+    h.g[2] = fmaf(gt_den, nn[2], -gpz);
+    // dtau/dn = -(p - mu) / den;  du/dt_u = (p - mu) / s_u
+    const float gn0 = -gt_den * px, gn1 = -gt_den * py, gn2 = -gt_den * pz;
+    const float au = gu / su, av = gv / sv;
+    const float gu0 = au * px, gu1 = au * py, gu2 = au * pz;
+    const float gv0 = av * px, gv1 = av * py, gv2 = av * pz;
+    const float inv = 1.0f / qn;
+    const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
+    // derivatives of the rotation columns with respect to (w, x, y, z)
+    const float dw = 2.0f * (z * gu1 - y * gu2 - z * gv0 + x * gv2 + y * gn0 - x * gn1);
+    const float dx = 2.0f * (y * gu1 + z * gu2 + y * gv0 - 2.0f * x * gv1 + w * gv2 + z * gn0 - w * gn1 -
+                             2.0f * x * gn2);
+    const float dy = 2.0f * (-2.0f * y * gu0 + x * gu1 - w * gu2 + x * gv0 + z * gv2 + w * gn0 + z * gn1 -
+                             2.0f * y * gn2);
+    const float dz = 2.0f * (-2.0f * z * gu0 + w * gu1 + x * gu2 - w * gv0 - 2.0f * z * gv1 + y * gv2 +
+                             x * gn0 + y * gn1);
+    const float proj = w * dw + x * dx + y * dy + z * dz;
+    h.g[3] = (dw - w * proj) * inv;
+    h.g[4] = (dx - x * proj) * inv;
+    h.g[5] = (dy - y * proj) * inv;
+    h.g[6] = (dz - z * proj) * inv;
+    acc.add<FM>(id, h);
+}
+
+// alpha of the k-buffer entry at Morton position pos (the same arithmetic as
+// the forward composite, so T is reproduced bit for bit).
+__device__ __forceinline__ float entry_alpha(const SceneView& sc, const Ray& ray, int pos)
+{
+    const SurfelRec s = load_rec(sc.rec, pos);
+    float tau, rho2;
+    plane_hit(s, ray, &tau, &rho2);
+    return alpha_of(s, rho2);
 }
 
 template <int K>
@@ -131,7 +229,7 @@ struct Checkpoint {
 template <int K, int FM>
 __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
                                         const Ray& ray, int64_t r, const OutPtrs& saved, bool use_saved,
-                                        const GradIn& gin, const GradOut& go, Stack& st, float4* ck,
+                                        const GradIn& gin, const GradAcc& go, Stack& st, float4* ck,
                                         int64_t ck_stride)
 {
     const float gO = gin.gO ? gin.gO[r] : 0.0f;
@@ -173,7 +271,7 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < kb.cnt && !done) {
-                T = T * (1.0f - kb.a[j]);
+                T = T * (1.0f - entry_alpha(sc, ray, kb.id[j]));
                 ++nh;
                 if (T < P.T_min) done = true;
             }
@@ -200,7 +298,7 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
             kb.clear();
             collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
 #pragma unroll
-            for (int j = 0; j < K; ++j) T = j < kb.cnt ? T * (1.0f - kb.a[j]) : T;
+            for (int j = 0; j < K; ++j) T = j < kb.cnt ? T * (1.0f - entry_alpha(sc, ray, kb.id[j])) : T;
             nb += kb.cnt;
             last_t = kb.t[K - 1];
             last_i = kb.id[K - 1];
@@ -212,12 +310,13 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             Tj[j] = T;
-            T = j < m ? T * (1.0f - kb.a[j]) : T;
+            T = j < m ? T * (1.0f - entry_alpha(sc, ray, kb.id[j])) : T;
         }
         for (int j = m - 1; j >= 0; --j) {
-            int id;
+            int pos;
             float Ti;
-            entry<K>(kb, Tj, j, &id, &Ti);
+            entry<K>(kb, Tj, j, &pos, &Ti);
+            const int id = __float_as_int(sc.rec[pos].c.w);
             grad_hit<FM>(raw, P.F, id, ray, Ti, S, gO, gF, gD, go);
         }
     }
@@ -229,15 +328,27 @@ __global__ __launch_bounds__(kBlock) void k_backward(SceneView sc, RawSurfels ra
                                                      OutPtrs saved, bool use_saved, GradIn gin, GradOut go, int* ovf,
                                                      int ovf_slots, float4* ck)
 {
-    __shared__ int lds_stack[kStackLds * kBlock];
-    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    __shared__ int hkeys[kHashSlots];
+    __shared__ float hvals[kLdsComp * kHashSlots];
+    const int tid = threadIdx.x;
+    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
-    Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
-             0};
+    // the re-march stack lives entirely in the global area (0 LDS slots)
+    Stack st{nullptr, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), tid, 0, 0};
     float4* myck = ck ? ck + gtid : nullptr;
-    for (int64_t r = gtid; r < R; r += nthr) {
-        const Ray ray = load_ray(ro, rd, r);
-        bwd_one<K, FM>(sc, raw, P, ray, r, saved, use_saved, gin, go, st, myck, nthr);
+    const GradAcc acc{hkeys, hvals, go, P.F};
+    const int64_t chunks = (R + kBlock - 1) / kBlock;
+    for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        acc.clear(tid);
+        __syncthreads();
+        const int64_t r = c * kBlock + tid;
+        if (r < R) {
+            const Ray ray = load_ray(ro, rd, r);
+            bwd_one<K, FM>(sc, raw, P, ray, r, saved, use_saved, gin, acc, st, myck, nthr);
+        }
+        __syncthreads();
+        acc.flush(tid);
+        __syncthreads();
     }
 }
 

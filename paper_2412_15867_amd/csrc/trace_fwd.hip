@@ -50,11 +50,14 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (j < kb.cnt && !done) {
-                    const float a = kb.a[j];
+                    const SurfelRec s = load_rec(sc.rec, kb.id[j]);
+                    float tau, rho2;
+                    plane_hit(s, ray, &tau, &rho2);
+                    const float a = alpha_of(s, rho2);
+                    const int id = __float_as_int(s.c.w);
                     const float w = T * a;
-                    const int id = kb.id[j];
                     O += w;
-                    D = fmaf(w, kb.t[j], D);
+                    D = fmaf(w, tau, D);
                     const float* f = sc.feat + static_cast<int64_t>(id) * P.F;
 #pragma unroll
                     for (int c = 0; c < FM; ++c)
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, i
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
     Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
-             0};
+             0, kStackLds};
     for (int64_t r = gtid; r < R; r += nthr) {
         const Ray ray = load_ray(ro, rd, r);
         trace_one<K, FM, BVH>(sc, P, ray, r, out, st);
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
     Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
-             0};
+             0, kStackLds};
     while (true) {
         if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1);
         __syncthreads();
