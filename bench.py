@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--points", type=int, default=256 * 256)
     ap.add_argument("--dirs", type=int, default=64)
     ap.add_argument("--k", type=int, default=16)
-    ap.add_argument("--hit-cap", type=int, default=64)
+    ap.add_argument("--hit-cap", type=int, default=256)
     ap.add_argument("--recompute", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)

@@ -72,6 +72,7 @@ typedef struct {
  *   t_min, t_max  hits need t_min < tau < t_max
  *   support_sigma hits need u^2 + v^2 <= support_sigma^2
  *   flags         IRGS_FLAG_* below
+ *   leaf_size     build only: surfels per BVH leaf cluster, 1..16 (0 = 4)
  * alpha_min and support_sigma are fixed at build time (they size the boxes);
  * tracing with other values returns IRGS_E_STATE. */
 typedef struct {
@@ -83,6 +84,7 @@ typedef struct {
     float t_max;
     float support_sigma;
     uint32_t flags;
+    int32_t leaf_size;
 } irgs_params;
 
 #define IRGS_FLAG_BRUTE_FORCE 1u /* trace: test every surfel, no BVH */

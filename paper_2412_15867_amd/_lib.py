@@ -29,7 +29,8 @@ class Surfels(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("k", c_i32), ("feature_dim", c_i32), ("alpha_min", c_f32), ("T_min", c_f32),
-                ("t_min", c_f32), ("t_max", c_f32), ("support_sigma", c_f32), ("flags", c_u32)]
+                ("t_min", c_f32), ("t_max", c_f32), ("support_sigma", c_f32), ("flags", c_u32),
+                ("leaf_size", c_i32)]
 
 
 class Out(ctypes.Structure):

@@ -37,6 +37,7 @@ struct irgs_scene_s {
     int* wscratch = nullptr;
     int n_wide = 0;
     int wide_depth = 0;
+    int leaf_size = kLeafDefault;
 };
 
 namespace {
@@ -133,6 +134,7 @@ BuildArgs build_args(irgs_scene s)
     a.wscratch = s->wscratch;
     a.n_wide = s->n_wide;
     a.wide_depth = s->wide_depth;
+    a.leaf_size = s->leaf_size;
     return a;
 }
 
@@ -290,6 +292,8 @@ irgs_status irgs_scene_build(irgs_scene s, const irgs_params* p, void* stream)
     if (!p) return fail(IRGS_E_INVALID, "params is NULL");
     if (!(p->alpha_min >= 0.0f) || !(p->support_sigma > 0.0f))
         return fail(IRGS_E_INVALID, "alpha_min >= 0 and support_sigma > 0 required");
+    if (p->leaf_size < 0 || p->leaf_size > 16) return fail(IRGS_E_INVALID, "leaf_size %d out of [0, 16]", p->leaf_size);
+    s->leaf_size = p->leaf_size == 0 ? kLeafDefault : p->leaf_size;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = s->n;
     hipError_t e = hipSuccess;
@@ -422,15 +426,15 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
         w[i].scene = it.scene;
         w[i].ray_begin = it.ray_begin;
         w[i].ray_count = it.ray_count;
-        w[i].chunk_begin = chunks;
+        w[i].chunk_begin = chunks;  // first slot of the item in the concatenation of all rays
         w[i].ro = it.ro;
         w[i].rd = it.rd;
         w[i].out = out_ptrs(&it.out);
-        chunks += (it.ray_count + kBlock - 1) / kBlock;
+        chunks += it.ray_count;
     }
     if (chunks == 0) return IRGS_OK;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const int grid = static_cast<int>(chunks < 2048 ? chunks : 2048);
+    const int grid = static_cast<int>(trace_threads(chunks) / kBlock);
     const size_t thr = static_cast<size_t>(grid) * kBlock;
     const size_t vb = sizeof(SceneView) * n_scenes, wb = sizeof(WorkItem) * n_items;
     const size_t items_off = (vb + 63) / 64 * 64;

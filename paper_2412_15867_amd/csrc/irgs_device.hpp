@@ -56,7 +56,7 @@ struct __align__(16) WideNode {
     int4 meta;  // unused
 };
 
-constexpr int kLeafMax = 4;  // surfels per cluster leaf (at most 16)
+constexpr int kLeafDefault = 4;  // surfels per cluster leaf (at most 16)
 
 __host__ __device__ __forceinline__ int cluster_ref(int first, int count)
 {
@@ -114,7 +114,7 @@ __device__ __forceinline__ void plane_hit(const SurfelRec& s, const Ray& r, floa
     const float wx = s.a.x - r.ox, wy = s.a.y - r.oy, wz = s.a.z - r.oz;
     const float den = dot3(s.b.x, s.b.y, s.b.z, r.dx, r.dy, r.dz);
     const float num = dot3(s.b.x, s.b.y, s.b.z, wx, wy, wz);
-    const float tau = num / den;
+    const float tau = num * __builtin_amdgcn_rcpf(den);  // den == 0: +-inf or NaN, rejected by the window
     const float px = fmaf(tau, r.dx, -wx), py = fmaf(tau, r.dy, -wy), pz = fmaf(tau, r.dz, -wz);
     const float u = dot3(px, py, pz, s.c.x, s.c.y, s.c.z);
     const float v = dot3(px, py, pz, s.d.x, s.d.y, s.d.z);
@@ -145,11 +145,25 @@ __device__ __forceinline__ SurfelRec load_rec(const SurfelRec* __restrict__ rec,
     return s;
 }
 
-// Strict lexicographic order on (tau, id).
-__device__ __forceinline__ bool key_less(float ta, int ia, float tb, int ib)
+// Hit keys: (tau, Morton position) packed into one 64-bit integer whose
+// unsigned order is the lexicographic order (the float maps to an unsigned
+// integer of the same order: sign-flipped when negative).
+__device__ __forceinline__ uint64_t hit_key(float tau, int pos)
 {
-    return ta < tb || (ta == tb && ia < ib);
+    const uint32_t u = __float_as_uint(tau);
+    const uint32_t m = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return (static_cast<uint64_t>(m) << 32) | static_cast<uint32_t>(pos);
 }
+
+__device__ __forceinline__ float key_tau(uint64_t k)
+{
+    const uint32_t m = static_cast<uint32_t>(k >> 32);
+    return __uint_as_float((m & 0x80000000u) ? (m & 0x7fffffffu) : ~m);
+}
+
+__device__ __forceinline__ int key_pos(uint64_t k) { return static_cast<int>(static_cast<uint32_t>(k)); }
+
+constexpr uint64_t kKeyNone = ~0ull;  // larger than every key
 
 // Slab test of a ray against a box, returning the entry distance; the box is
 // accepted when it overlaps [lo, hi] along the ray.  `hi` must be finite.

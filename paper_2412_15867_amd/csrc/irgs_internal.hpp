@@ -30,6 +30,7 @@ struct BuildArgs {
     WideNode* wnodes;       // up to max(N - 1, 1) wide nodes
     int4* wsrc;             // per wide node and slot: (binary parent << 1 | side), -1 = empty
     int* wscratch;          // 2 * max(N - 1, 1) + 4 ints: frontiers and counters
+    int leaf_size;          // surfels per cluster leaf (1..16)
     int n_wide;             // out (host): wide nodes built; also the refit input
     int wide_depth;         // out (host): levels of the wide tree
 };
@@ -97,7 +98,8 @@ hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const Tra
                            hipStream_t st);
 
 // Packed launch over work items of several scenes (serving).  Item i owns
-// the chunks [chunk_begin, chunk_begin + ceil(ray_count / kBlock)).
+// the slots [chunk_begin, chunk_begin + ray_count) of the concatenation of
+// every item's rays.
 struct WorkItem {
     int32_t scene;
     int32_t pad;

@@ -452,13 +452,14 @@ __device__ __forceinline__ void set_wide_box(WideNode* w, int slot, const float*
 
 // One level of the top-down collapse: wide node w stands for binary node b;
 // its up-to-four children are found by repeatedly opening the candidate with
-// the largest box area, as long as that candidate holds more than kLeafMax
-// surfels.  Candidates with at most kLeafMax surfels become cluster leaves
+// the largest box area, as long as that candidate holds more than leaf_max
+// surfels.  Candidates with at most leaf_max surfels become cluster leaves
 // (their surfels are contiguous in Morton order); larger ones become new wide
 // nodes of the next level.
 __global__ void k_collapse(int nfront, const int* __restrict__ front_in, int* __restrict__ front_out,
                            int* __restrict__ counts, int* __restrict__ wide_src, const BvhNode* __restrict__ bn,
-                           const int2* __restrict__ brange, WideNode* __restrict__ wn, int4* __restrict__ wsrc)
+                           const int2* __restrict__ brange, WideNode* __restrict__ wn, int4* __restrict__ wsrc,
+                           int leaf_max)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nfront) return;
@@ -482,7 +483,7 @@ __global__ void k_collapse(int nfront, const int* __restrict__ front_in, int* __
         float ba = -1.0f;
         for (int c = 0; c < m; ++c) {
             const bool internal = (ref[c] & kLeafBit) == 0;
-            if (internal && brange[ref[c]].y > kLeafMax && area[c] > ba) {
+            if (internal && brange[ref[c]].y > leaf_max && area[c] > ba) {
                 best = c;
                 ba = area[c];
             }
@@ -517,7 +518,7 @@ __global__ void k_collapse(int nfront, const int* __restrict__ front_in, int* __
         const int r = ref[c];
         if (r & kLeafBit) {
             chp[c] = cluster_ref(r & ~kLeafBit, 1);
-        } else if (brange[r].y <= kLeafMax) {
+        } else if (brange[r].y <= leaf_max) {
             chp[c] = cluster_ref(brange[r].x, brange[r].y);
         } else {
             const int nw = atomicAdd(&counts[0], 1);
@@ -664,7 +665,7 @@ hipError_t lbvh_build(BuildArgs& a, void* scratch, hipStream_t st)
             e = fill_u32(counts + 1, 1, 0u, st);
             if (e != hipSuccess) return e;
             k_collapse<<<blocks_for(nfront, 128), 128, 0, st>>>(nfront, fa, fb, counts, wide_src, a.nodes,
-                                                                  a.brange, a.wnodes, a.wsrc);
+                                                                  a.brange, a.wnodes, a.wsrc, a.leaf_size);
             e = hipGetLastError();
             if (e == hipSuccess) e = hipMemcpyAsync(&nfront, counts + 1, sizeof(int), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);

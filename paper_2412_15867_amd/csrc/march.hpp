@@ -20,57 +20,52 @@ struct Counters {
     int nodes = 0, tests = 0, inserts = 0, rounds = 0;
 };
 
-// The k-buffer holds (tau, Morton position) keys, ascending.  Equal depths
-// are ordered by Morton position, which every kernel shares.  alpha and the
-// surfel id are re-read from the record when the entry is composited.
+// The k-buffer holds hit keys (tau, Morton position), ascending.  Equal
+// depths are ordered by Morton position, which every kernel shares.  alpha
+// and the surfel id are re-read from the record when an entry is composited.
 template <int K>
 struct KBuf {
-    float t[K];
-    int id[K];
+    uint64_t k[K];
     int cnt;
 
     __device__ __forceinline__ void clear()
     {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            t[j] = __int_as_float(0x7f800000);  // +inf
-            id[j] = 0x7fffffff;
-        }
+        for (int j = 0; j < K; ++j) k[j] = kKeyNone;
         cnt = 0;
     }
 
     __device__ __forceinline__ bool full() const { return cnt >= K; }
+    __device__ __forceinline__ uint64_t last() const { return k[K - 1]; }
+    __device__ __forceinline__ int pos(int j) const { return key_pos(k[j]); }
 
-    // Insert (tt, ii); the largest key falls off the end when full.
-    __device__ __forceinline__ void insert(float tt, int ii)
+    // Insert a key; the largest falls off the end when full.
+    __device__ __forceinline__ void insert(uint64_t key)
     {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const bool lt = key_less(tt, ii, t[j], id[j]);
-            const float t2 = lt ? t[j] : tt;
-            const int i2 = lt ? id[j] : ii;
-            t[j] = lt ? tt : t[j];
-            id[j] = lt ? ii : id[j];
-            tt = t2;
-            ii = i2;
+            const bool lt = key < k[j];
+            const uint64_t t = lt ? k[j] : key;
+            k[j] = lt ? key : k[j];
+            key = t;
         }
         cnt = cnt < K ? cnt + 1 : K;
     }
 };
 
 // Offer the record at Morton position `pos` to the buffer: Eq. 6-7 test,
-// resume-key window, and the K-th-key cut once full.
+// above the resume key, below the K-th key once full.
 template <int K>
 __device__ __forceinline__ void offer(KBuf<K>& kb, const SurfelRec& s, int pos, const Ray& ray, float t_min,
-                                      float t_max, float last_t, int last_i, Counters& ct)
+                                      float t_max, uint64_t after, Counters& ct)
 {
     ++ct.tests;
     float tau, rho2;
     if (!hit_test(s, ray, t_min, t_max, &tau, &rho2)) return;
-    if (!key_less(last_t, last_i, tau, pos)) return;
-    if (!key_less(tau, pos, kb.t[K - 1], kb.id[K - 1])) return;
+    const uint64_t key = hit_key(tau, pos);
+    if (key <= after || key >= kb.last()) return;
     ++ct.inserts;
-    kb.insert(tau, pos);
+    kb.insert(key);
 }
 
 // Per-lane traversal stack: the first `lds_slots` entries live in LDS
@@ -100,16 +95,16 @@ struct Stack {
 };
 
 // One round of collection by traversal of the 4-wide tree.  Child boxes
-// are culled against the window [max(t_min, last_t), min(t_max, K-th key)];
+// are culled against the window [max(t_min, resume depth), min(t_max, K-th key)];
 // cluster leaves are tested on the spot, inner children are visited nearest
 // first (the others are pushed farthest first).
 template <int K>
 __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, const Ray& ray, float ix, float iy,
-                                            float iz, float t_min, float t_max, float last_t, int last_i, Stack& st,
+                                            float iz, float t_min, float t_max, uint64_t after, Stack& st,
                                             Counters& ct)
 {
     ++ct.rounds;
-    const float lo = fmaxf(t_min, last_t);
+    const float lo = after == 0 ? t_min : fmaxf(t_min, key_tau(after));
     const float tmax_c = fminf(t_max, 3.0e38f);
     const float inf = __int_as_float(0x7f800000);
     st.sp = 0;
@@ -119,7 +114,7 @@ __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, co
         const float4* np = reinterpret_cast<const float4*>(sc.wnodes + node);
         const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5];
         const int4 ch = reinterpret_cast<const int4*>(np)[6];
-        const float hi = kb.full() ? fminf(kb.t[K - 1], tmax_c) : tmax_c;
+        const float hi = kb.full() ? fminf(key_tau(kb.last()), tmax_c) : tmax_c;
         float te[4];
         bool h[4];
         h[0] = box_hit(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[0]);
@@ -144,7 +139,7 @@ __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, co
             const int first = (r & ~kLeafBit) >> 4;
             const int cnt = (r & 15) + 1;
             for (int q = first; q < first + cnt; ++q)
-                offer<K>(kb, load_rec(sc.rec, q), q, ray, t_min, t_max, last_t, last_i, ct);
+                offer<K>(kb, load_rec(sc.rec, q), q, ray, t_min, t_max, after, ct);
         }
         // sort the four (entry distance, child) pairs ascending
 #define IRGS_CSWAP(a, b)                                      \
@@ -178,10 +173,10 @@ __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, co
 // The record index is uniform across the wave, so loads are broadcast.
 template <int K>
 __device__ __forceinline__ void collect_all(KBuf<K>& kb, const SceneView& sc, const Ray& ray, float t_min,
-                                            float t_max, float last_t, int last_i, Counters& ct)
+                                            float t_max, uint64_t after, Counters& ct)
 {
     ++ct.rounds;
-    for (int i = 0; i < sc.n; ++i) offer<K>(kb, load_rec(sc.rec, i), i, ray, t_min, t_max, last_t, last_i, ct);
+    for (int i = 0; i < sc.n; ++i) offer<K>(kb, load_rec(sc.rec, i), i, ray, t_min, t_max, after, ct);
 }
 
 __device__ __forceinline__ bool ray_valid(const Ray& r)

@@ -206,25 +206,18 @@ __device__ __forceinline__ float entry_alpha(const SceneView& sc, const Ray& ray
 }
 
 template <int K>
-__device__ __forceinline__ void entry(const KBuf<K>& kb, const float* Tj, int j, int* id, float* T)
+__device__ __forceinline__ void entry(const KBuf<K>& kb, const float* Tj, int j, int* pos, float* T)
 {
     int ri = 0;
     float rt = 0.0f;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        ri = q == j ? kb.id[q] : ri;
+        ri = q == j ? kb.pos(q) : ri;
         rt = q == j ? Tj[q] : rt;
     }
-    *id = ri;
+    *pos = ri;
     *T = rt;
 }
-
-struct Checkpoint {
-    float last_t;
-    int last_i;
-    float T;
-    int nb;  // hits composited before this round
-};
 
 template <int K, int FM>
 __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
@@ -256,32 +249,30 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
     // ---- re-march: pass 1 records the state at the start of each round
     Counters ct;
     const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
-    float last_t = -__int_as_float(0x7f800000);
-    int last_i = -1;
+    uint64_t after = 0;
     float T = 1.0f;
     int nh = 0;
     int rounds = 0;
     bool done = false;
     while (!done) {
         if (rounds < kBwdCheckpoints)
-            ck[rounds * ck_stride] = make_float4(last_t, __int_as_float(last_i), T, __int_as_float(nh));
+            ck[rounds * ck_stride] = make_float4(__uint_as_float(static_cast<uint32_t>(after >> 32)),
+                                                 __uint_as_float(static_cast<uint32_t>(after)), T, __int_as_float(nh));
         KBuf<K> kb;
         kb.clear();
-        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
+        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < kb.cnt && !done) {
-                T = T * (1.0f - entry_alpha(sc, ray, kb.id[j]));
+                T = T * (1.0f - entry_alpha(sc, ray, kb.pos(j)));
                 ++nh;
                 if (T < P.T_min) done = true;
             }
         }
-        if (kb.cnt < K) {
+        if (kb.cnt < K)
             done = true;
-        } else {
-            last_t = kb.t[K - 1];
-            last_i = kb.id[K - 1];
-        }
+        else
+            after = kb.last();
         ++rounds;
     }
     const int total = nh;
@@ -289,28 +280,26 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
     for (int rr = rounds - 1; rr >= 0; --rr) {
         const int base = rr < kBwdCheckpoints ? rr : kBwdCheckpoints - 1;
         float4 c4 = ck[base * ck_stride];
-        last_t = c4.x;
-        last_i = __float_as_int(c4.y);
+        after = (static_cast<uint64_t>(__float_as_uint(c4.x)) << 32) | __float_as_uint(c4.y);
         T = c4.z;
         int nb = __float_as_int(c4.w);
         KBuf<K> kb;
         for (int adv = base; adv < rr; ++adv) {  // rounds past the last checkpoint
             kb.clear();
-            collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
+            collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
 #pragma unroll
-            for (int j = 0; j < K; ++j) T = j < kb.cnt ? T * (1.0f - entry_alpha(sc, ray, kb.id[j])) : T;
+            for (int j = 0; j < K; ++j) T = j < kb.cnt ? T * (1.0f - entry_alpha(sc, ray, kb.pos(j))) : T;
             nb += kb.cnt;
-            last_t = kb.t[K - 1];
-            last_i = kb.id[K - 1];
+            after = kb.last();
         }
         kb.clear();
-        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
+        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
         const int m = min(kb.cnt, total - nb);
         float Tj[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             Tj[j] = T;
-            T = j < m ? T * (1.0f - entry_alpha(sc, ray, kb.id[j])) : T;
+            T = j < m ? T * (1.0f - entry_alpha(sc, ray, kb.pos(j))) : T;
         }
         for (int j = m - 1; j >= 0; --j) {
             int pos;

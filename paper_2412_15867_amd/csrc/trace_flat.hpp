@@ -1,0 +1,236 @@
+// Forward trace as a flat per-lane state machine (BVH path).
+//
+// The k-buffer marching of Sec. 3.2 nests three loops per ray -- rounds,
+// traversal steps inside a round, and the composite of a round's buffer.
+// Written as nested loops, a wave of 64 rays runs every level in lockstep:
+// lanes that finished a round (or their ray) idle until the slowest lane of
+// the wave catches up.  Here each loop iteration advances every lane by one
+// unit of its own work:
+//   TRAV  visit one wide node (4 box tests; children pushed far to near, the
+//         nearest becomes the current item) or test one surfel of a cluster;
+//         an empty stack ends the round;
+//   COMP  composite the nearest buffered hit (Eq. 2: w = T alpha, T *= 1 - a)
+//         or, with the buffer drained, start the next round or finish the ray;
+//   FETCH take the lane's next ray.
+// Per ray the arithmetic and its order are exactly those of the nested form,
+// so results are bit-identical; only the interleaving across lanes changes.
+#pragma once
+
+#include "irgs_internal.hpp"
+#include "march.hpp"
+
+namespace irgs {
+
+constexpr int kItemEmpty = 0x7fffffff;  // no current item (stack drained)
+
+// Where a lane's rays come from and where their results go.
+struct LaneRay {
+    int64_t r;  // ray index within its output arrays
+    int item;   // work item (packed launches), 0 otherwise
+    SceneView sc;
+};
+
+// One scene, rays [0, R), lane g takes rays g, g + stride, ...
+struct PlainSource {
+    SceneView sc;
+    OutPtrs o;
+    const float* ro;
+    const float* rd;
+    int64_t R;
+    int64_t stride;
+
+    __device__ __forceinline__ bool next(int64_t& slot, LaneRay& lr, Ray& ray) const
+    {
+        if (slot >= R) return false;
+        lr.r = slot;
+        lr.item = 0;
+        lr.sc = sc;
+        ray = load_ray(ro, rd, slot);
+        slot += stride;
+        return true;
+    }
+    __device__ __forceinline__ const OutPtrs& out(const LaneRay&) const { return o; }
+};
+
+// Several requests over several scenes: a lane's slot indexes the
+// concatenation of the items' rays; the owning item is found by bisection.
+struct PackedSource {
+    const SceneView* scenes;
+    const WorkItem* items;
+    int n_items;
+    int64_t total;
+    int64_t stride;
+
+    __device__ __forceinline__ bool next(int64_t& slot, LaneRay& lr, Ray& ray) const
+    {
+        if (slot >= total) return false;
+        int lo = 0, hi = n_items - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].chunk_begin <= slot)  // chunk_begin holds the item's first slot here
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const WorkItem& it = items[lo];
+        const int64_t local = slot - it.chunk_begin;
+        lr.r = it.ray_begin + local;
+        lr.item = lo;
+        lr.sc = scenes[it.scene];
+        ray = load_ray(it.ro, it.rd, lr.r);
+        slot += stride;
+        return true;
+    }
+    __device__ __forceinline__ const OutPtrs& out(const LaneRay& lr) const { return items[lr.item].out; }
+};
+
+template <int FM, class Source>
+__device__ __forceinline__ void write_result(const Source& src, const LaneRay& lr, float O, float D, float T,
+                                             const float* acc, int nh, const Counters& ct)
+{
+    const OutPtrs& out = src.out(lr);
+    const int64_t r = lr.r;
+    const int F = lr.sc.F;
+    out.O[r] = O;
+    out.D[r] = D;
+#pragma unroll
+    for (int c = 0; c < FM; ++c)
+        if (c < F) out.feat[r * F + c] = acc[c];
+    if (out.T) out.T[r] = T;
+    if (out.n_hits) out.n_hits[r] = nh;
+    if (out.counters)
+        reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
+}
+
+template <int K, int FM, class Source>
+__device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot, const TraceParams& P, Stack& st)
+{
+    enum { kTrav = 0, kComp = 1, kFetch = 2 };
+    const float inf = __int_as_float(0x7f800000);
+    int64_t slot = first_slot;
+    LaneRay lr;
+    Ray ray;
+    float ix = 0.0f, iy = 0.0f, iz = 0.0f;
+    float T = 1.0f, O = 0.0f, D = 0.0f;
+    float acc[FM];
+    int nh = 0;
+    uint64_t after = 0, round_last = 0;
+    bool round_full = false, term = false;
+    int cur = kItemEmpty;
+    int mode = kFetch;
+    KBuf<K> kb;
+    kb.clear();
+    Counters ct;
+    while (true) {
+        if (mode == kFetch) {
+            if (!src.next(slot, lr, ray)) break;
+            T = 1.0f, O = 0.0f, D = 0.0f, nh = 0;
+#pragma unroll
+            for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
+            ct = Counters();
+            after = 0;
+            term = false;
+            kb.clear();
+            if (lr.sc.n <= 0 || !ray_valid(ray)) {
+                write_result<FM>(src, lr, O, D, T, acc, nh, ct);
+                continue;
+            }
+            ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
+            cur = 0;
+            st.sp = 0;
+            ++ct.rounds;
+            mode = kTrav;
+        }
+        if (mode == kTrav) {
+            if (cur == kItemEmpty) {
+                round_full = kb.full();
+                round_last = kb.last();
+                mode = kComp;
+            } else if (cur >= 0) {
+                ++ct.nodes;
+                const float4* np = reinterpret_cast<const float4*>(lr.sc.wnodes + cur);
+                const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5];
+                const int4 ch = reinterpret_cast<const int4*>(np)[6];
+                const float lo = after == 0 ? P.t_min : fmaxf(P.t_min, key_tau(after));
+                const float tmax_c = fminf(P.t_max, 3.0e38f);
+                const float hi = kb.full() ? fminf(key_tau(kb.last()), tmax_c) : tmax_c;
+                float key[4];
+                int ref[4] = {ch.x, ch.y, ch.z, ch.w};
+                float te;
+                key[0] = box_hit(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
+                             ? te : inf;
+                key[1] = box_hit(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
+                             ? te : inf;
+                key[2] = box_hit(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
+                             ? te : inf;
+                key[3] = box_hit(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
+                             ? te : inf;
+#define IRGS_CSWAP(a, b)                    \
+    if (key[b] < key[a]) {                  \
+        const float tk = key[a];            \
+        key[a] = key[b];                    \
+        key[b] = tk;                        \
+        const int tr = ref[a];              \
+        ref[a] = ref[b];                    \
+        ref[b] = tr;                        \
+    }
+                IRGS_CSWAP(0, 1)
+                IRGS_CSWAP(2, 3)
+                IRGS_CSWAP(0, 2)
+                IRGS_CSWAP(1, 3)
+                IRGS_CSWAP(1, 2)
+#undef IRGS_CSWAP
+                if (key[3] < inf) st.push(ref[3]);
+                if (key[2] < inf) st.push(ref[2]);
+                if (key[1] < inf) st.push(ref[1]);
+                cur = key[0] < inf ? ref[0] : (st.sp > 0 ? st.pop() : kItemEmpty);
+            } else {
+                const int first = (cur & ~kLeafBit) >> 4;
+                const int cnt = (cur & 15) + 1;
+                offer<K>(kb, load_rec(lr.sc.rec, first), first, ray, P.t_min, P.t_max, after, ct);
+                cur = cnt > 1 ? cluster_ref(first + 1, cnt - 1) : (st.sp > 0 ? st.pop() : kItemEmpty);
+            }
+        }
+        if (mode == kComp) {
+            if (kb.cnt > 0 && !term) {
+                const int pos = kb.pos(0);
+#pragma unroll
+                for (int j = 0; j < K - 1; ++j) kb.k[j] = kb.k[j + 1];
+                kb.k[K - 1] = kKeyNone;
+                --kb.cnt;
+                const SurfelRec s = load_rec(lr.sc.rec, pos);
+                float tau, rho2;
+                plane_hit(s, ray, &tau, &rho2);
+                const float a = alpha_of(s, rho2);
+                const int id = __float_as_int(s.c.w);
+                const float w = T * a;
+                O += w;
+                D = fmaf(w, tau, D);
+                const float* f = lr.sc.feat + static_cast<int64_t>(id) * lr.sc.F;
+#pragma unroll
+                for (int c = 0; c < FM; ++c)
+                    if (c < lr.sc.F) acc[c] = fmaf(w, f[c], acc[c]);
+                const OutPtrs& out = src.out(lr);
+                if (out.hit_ids && nh < out.H_cap) {
+                    out.hit_ids[lr.r * out.H_cap + nh] = id;
+                    if (out.hit_T) out.hit_T[lr.r * out.H_cap + nh] = T;
+                }
+                T = T * (1.0f - a);
+                ++nh;
+                if (T < P.T_min) term = true;
+            } else if (term || !round_full) {
+                write_result<FM>(src, lr, O, D, T, acc, nh, ct);
+                mode = kFetch;
+            } else {
+                after = round_last;
+                kb.clear();
+                cur = 0;
+                st.sp = 0;
+                ++ct.rounds;
+                mode = kTrav;
+            }
+        }
+    }
+}
+
+}  // namespace irgs

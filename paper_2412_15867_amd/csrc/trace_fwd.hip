@@ -11,6 +11,7 @@
 
 #include "irgs_internal.hpp"
 #include "march.hpp"
+#include "trace_flat.hpp"
 
 namespace irgs {
 
@@ -37,20 +38,19 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
     Counters ct;
     if (sc.n > 0 && ray_valid(ray)) {
         const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
-        float last_t = -__int_as_float(0x7f800000);
-        int last_i = -1;
+        uint64_t after = 0;  // resume key: hits strictly above it (0 = from the start)
         bool done = false;
         while (!done) {
             KBuf<K> kb;
             kb.clear();
             if (BVH)
-                collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, last_t, last_i, st, ct);
+                collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
             else
-                collect_all<K>(kb, sc, ray, P.t_min, P.t_max, last_t, last_i, ct);
+                collect_all<K>(kb, sc, ray, P.t_min, P.t_max, after, ct);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (j < kb.cnt && !done) {
-                    const SurfelRec s = load_rec(sc.rec, kb.id[j]);
+                    const SurfelRec s = load_rec(sc.rec, kb.pos(j));
                     float tau, rho2;
                     plane_hit(s, ray, &tau, &rho2);
                     const float a = alpha_of(s, rho2);
@@ -71,12 +71,10 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
                     if (T < P.T_min) done = true;
                 }
             }
-            if (kb.cnt < K) {
+            if (kb.cnt < K)
                 done = true;
-            } else {
-                last_t = kb.t[K - 1];
-                last_i = kb.id[K - 1];
-            }
+            else
+                after = kb.last();
         }
     }
     out.O[r] = O;
@@ -100,9 +98,14 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, i
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
     Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
              0, kStackLds};
-    for (int64_t r = gtid; r < R; r += nthr) {
-        const Ray ray = load_ray(ro, rd, r);
-        trace_one<K, FM, BVH>(sc, P, ray, r, out, st);
+    if (BVH) {
+        const PlainSource src{sc, out, ro, rd, R, nthr};
+        trace_flat<K, FM>(src, gtid, P, st);
+    } else {
+        for (int64_t r = gtid; r < R; r += nthr) {
+            const Ray ray = load_ray(ro, rd, r);
+            trace_one<K, FM, false>(sc, P, ray, r, out, st);
+        }
     }
 }
 
@@ -152,41 +155,15 @@ hipError_t launch_b(const SceneView& sc, const TraceParams& P, int k, int64_t R,
 template <int K, int FM>
 __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__ scenes,
                                                    const WorkItem* __restrict__ items, int n_items,
-                                                   int64_t n_chunks, TraceParams P, int* ovf, int ovf_slots,
-                                                   int* counter)
+                                                   int64_t n_rays, TraceParams P, int* ovf, int ovf_slots)
 {
     __shared__ int lds_stack[kStackLds * kBlock];
-    __shared__ int s_chunk;
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
     Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
              0, kStackLds};
-    while (true) {
-        if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1);
-        __syncthreads();
-        const int64_t c = s_chunk;
-        __syncthreads();
-        if (c >= n_chunks) break;
-        // the item owning chunk c: last item with chunk_begin <= c
-        int lo = 0, hi = n_items - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].chunk_begin <= c)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const WorkItem& it = items[lo];
-        const SceneView sc = scenes[it.scene];
-        TraceParams Pi = P;
-        Pi.F = sc.F;
-        const int64_t local = (c - it.chunk_begin) * kBlock + threadIdx.x;
-        if (local < it.ray_count) {
-            const int64_t r = it.ray_begin + local;
-            const Ray ray = load_ray(it.ro, it.rd, r);
-            trace_one<K, FM, true>(sc, Pi, ray, r, it.out, st);
-        }
-    }
+    const PackedSource src{scenes, items, n_items, n_rays, nthr};
+    trace_flat<K, FM>(src, gtid, P, st);
 }
 
 template <int K, int FM>
@@ -194,7 +171,8 @@ hipError_t launch_packed_kf(const SceneView* scenes, const WorkItem* items, int 
                             const TraceParams& P, int* ovf, int ovf_slots, int* counter, int grid_blocks,
                             hipStream_t st)
 {
-    k_packed<K, FM><<<grid_blocks, kBlock, 0, st>>>(scenes, items, n_items, n_chunks, P, ovf, ovf_slots, counter);
+    (void)counter;
+    k_packed<K, FM><<<grid_blocks, kBlock, 0, st>>>(scenes, items, n_items, n_chunks, P, ovf, ovf_slots);
     return hipGetLastError();
 }
 

@@ -69,13 +69,14 @@ class Scene:
     keep them alive, and call ``refit()`` after changing them in place."""
 
     def __init__(self, mu, quat, scale, opacity, feat, alpha_min: float = DEFAULT_ALPHA_MIN,
-                 support_sigma: float = DEFAULT_SIGMA, build: bool = True):
+                 support_sigma: float = DEFAULT_SIGMA, build: bool = True, leaf_size: int = 0):
         n = mu.shape[0]
         F = feat.shape[1] if feat.dim() == 2 else 1
         self.device = mu.device
         self.n, self.F = int(n), int(F)
         self.alpha_min = float(alpha_min)
         self.support_sigma = float(support_sigma)
+        self.leaf_size = int(leaf_size)
         self._set_tensors(mu, quat, scale, opacity, feat)
         h = ctypes.c_void_p()
         check(_lib.lib().irgs_scene_create(self.n, self.F, ctypes.byref(self._surfels()), ctypes.byref(h)),
@@ -106,7 +107,7 @@ class Scene:
 
     def params(self, cfg: TraceConfig, flags: int = 0) -> _lib.Params:
         return _lib.Params(int(cfg.k), self.F, self.alpha_min, float(cfg.T_min), float(cfg.t_min),
-                           float(cfg.t_max), self.support_sigma, flags)
+                           float(cfg.t_max), self.support_sigma, flags, self.leaf_size)
 
     def set_params(self, mu, quat, scale, opacity, feat):
         self._set_tensors(mu, quat, scale, opacity, feat)
@@ -286,7 +287,7 @@ def trace_packed(scenes: Sequence[Scene], items: Sequence[tuple], cfg: Optional[
     dev = scenes[0].device
     Fmax = max(s.F for s in scenes)
     p = _lib.Params(int(cfg.k), Fmax, scenes[0].alpha_min, float(cfg.T_min), float(cfg.t_min),
-                    float(cfg.t_max), scenes[0].support_sigma, 0)
+                    float(cfg.t_max), scenes[0].support_sigma, 0, 0)
     handles = (ctypes.c_void_p * len(scenes))(*[s.handle.value for s in scenes])
     works = (_lib.Work * max(len(items), 1))()
     for i, (si, ro, rd, res) in enumerate(items):

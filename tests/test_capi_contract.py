@@ -67,14 +67,14 @@ def test_unbuilt_scene_and_bad_params_are_rejected(L):
     h = ctypes.c_void_p()
     s = _lib.Surfels(1, 1, 1, 1, 1)  # never dereferenced: nothing runs before the checks
     assert L.irgs_scene_create(4, 3, ctypes.byref(s), ctypes.byref(h)) == _lib.IRGS_OK
-    p = _lib.Params(16, 3, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0)
+    p = _lib.Params(16, 3, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0, 0)
     out = _lib.Out(1, 1, 1, None, None, None, None, 0)
     assert L.irgs_trace(h, ctypes.byref(p), 4, 1, 1, ctypes.byref(out), None) == _lib.IRGS_E_STATE
     assert b"not built" in L.irgs_last_error()
-    p_bad = _lib.Params(3, 3, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0)
+    p_bad = _lib.Params(3, 3, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0, 0)
     assert L.irgs_trace(h, ctypes.byref(p_bad), 4, 1, 1, ctypes.byref(out), None) == _lib.IRGS_E_INVALID
     assert b"k = 3" in L.irgs_last_error()
-    p_f = _lib.Params(16, 8, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0)
+    p_f = _lib.Params(16, 8, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0, 0)
     assert L.irgs_trace(h, ctypes.byref(p_f), 4, 1, 1, ctypes.byref(out), None) == _lib.IRGS_E_INVALID
     assert L.irgs_trace(h, ctypes.byref(p), -1, 1, 1, ctypes.byref(out), None) == _lib.IRGS_E_INVALID
     assert L.irgs_trace(None, ctypes.byref(p), 4, 1, 1, ctypes.byref(out), None) == _lib.IRGS_E_INVALID
@@ -89,7 +89,7 @@ def test_unbuilt_scene_and_bad_params_are_rejected(L):
 
 def test_packed_rejects_bad_arguments(L):
     from paper_2412_15867_amd import _lib
-    p = _lib.Params(8, 3, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0)
+    p = _lib.Params(8, 3, 1 / 255, 1e-4, 0.0, float("inf"), 3.0, 0, 0)
     arr = (ctypes.c_void_p * 1)(None)
     assert L.irgs_trace_packed(arr, 1, ctypes.byref(p), None, 0, None) == _lib.IRGS_E_INVALID
     assert L.irgs_trace_packed(None, 0, ctypes.byref(p), None, 0, None) == _lib.IRGS_E_INVALID
