@@ -11,7 +11,9 @@ bwd)), with per-phase timings, the roofline of the dominant kernel measured
 live with HIP events, and the FP64 oracle timed on the host for a bounded
 sample of the same workload.
 
-Other workloads (--workload): c2 (200K surfels, forward only), serve (three
+Other workloads (--workload): c1 (4,096-surfel cube, 64x64 camera rays) and
+c2 (200K surfels, 4.2M MC rays), forward only against the brute-force GPU
+tracer; serve (three
 resident scenes, Poisson request stream, packed launches vs one launch per
 request), c5 (5M surfels, 33.5M rays, training-like step with perturbation
 and refit).
@@ -204,12 +206,216 @@ def run_c3(args):
     return line
 
 
+def _time_launches(fn, reps=3):
+    import torch
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def run_forward_only(args, small: bool):
+    """c1: 4,096-surfel cube, 64x64 pinhole rays; c2: 200K surfels, 4.2M MC
+    rays.  Forward only, BVH tracer vs the brute-force GPU tracer (plain)."""
+    import torch
+    from paper_2412_15867_amd import Scene, TraceConfig, synth, trace
+    dev = torch.device("cuda:0")
+    if small:
+        sc = synth.cube_scene()
+        ro, rd = synth.pinhole_rays(64, 64)
+        name = "4096 surfels (cube), 64x64 pinhole rays, forward, F=3"
+        n_brute = ro.shape[0]
+    else:
+        sc, ro, rd = gen_surface_workload(200_000, 256 * 256, 64)
+        name = "200000 surfels (8 spheres + 4 planes, F=8), 256x256x64 MC rays, forward"
+        n_brute = 16384
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    scene = Scene(*(t(a) for a in sc.astuple()))
+    ro_d, rd_d = t(ro), t(rd)
+    R = ro.shape[0]
+    cfg = TraceConfig(k=args.k)
+    res = trace(scene, ro_d, rd_d, cfg)
+    torch.cuda.synchronize()
+    ms = _time_launches(lambda: trace(scene, ro_d, rd_d, cfg, out=res), reps=max(3, args.steps))
+    n_hits = res.n_hits.cpu().numpy()
+    sub = slice(0, n_brute)
+    bres = trace(scene, ro_d[sub], rd_d[sub], TraceConfig(k=args.k, brute_force=True))
+    torch.cuda.synchronize()
+    bms = _time_launches(lambda: trace(scene, ro_d[sub], rd_d[sub], TraceConfig(k=args.k, brute_force=True),
+                                       out=bres), reps=2)
+    same = bool(torch.equal(bres.opacity, res.opacity[sub]) and torch.equal(bres.n_hits, res.n_hits[sub]))
+    fb = fwd_bytes(n_hits, sc.F)
+    ach = fb / (ms * 1e-3) / 1e9
+    line = {"metric": "Mrays/s fwd", "value": round(R / (ms * 1e-3) / 1e6, 3), "unit": "Mrays/s", "n_gpus": 1,
+            "steps": max(3, args.steps), "warmup": 1, "ms_per_step": round(ms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": name + f", k={args.k}", "surfels": sc.n, "rays": R},
+            "hits_per_ray": round(float(n_hits.mean()), 3),
+            "plain_gpu_bruteforce": {"mrays_s": round(n_brute / (bms * 1e-3) / 1e6, 3), "rays": n_brute,
+                                     "ms": round(bms, 3), "bitwise_equal_to_bvh": same},
+            "roofline": {"bound": "hbm", "kernel": "k_trace (forward)", "achieved": round(ach, 3),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None}}
+    if not args.no_cpu_baseline:
+        import oracle
+        g = np.random.default_rng(7)
+        m = min(R, 4096 if small else 2048)
+        idx = np.sort(g.choice(R, m, replace=False))
+        t0 = time.perf_counter()
+        oracle.trace(sc.astuple(), ro[idx], rd[idx])
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(m / dt / 1e6, 6), "unit": "Mrays/s", "cores": oracle.max_threads(),
+                                "kind": "oracle", "sample": f"{m} seeded rays, brute force FP64 forward"}
+    scene.close()
+    return line
+
+
+def run_serve(args):
+    """Three resident scenes (300K, 1M, 3M surfels); Poisson arrivals of
+    requests with log-uniform ray counts in [1K, 4M] over device ray pools;
+    continuous batching into packed launches vs one launch per request."""
+    import torch
+    from paper_2412_15867_amd import Scene, TraceConfig, synth, trace, trace_packed, alloc_result
+    from paper_2412_15867_amd.serve import Server, latency_stats, run_open_loop, run_per_request
+    dev = torch.device("cuda:0")
+    lay = synth.layout()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    sizes = (300_000, 1_000_000, 3_000_000)
+    scenes = []
+    for n in sizes:
+        sc = synth.surface_scene(n, F=8, lay=lay)
+        scenes.append(Scene(*(t(a) for a in sc.astuple())))
+        del sc
+    ro, rd = synth.mc_rays(256 * 256, 64, lay=lay)
+    pool_o, pool_d = t(ro), t(rd)
+    P = pool_o.shape[0]
+    cfg = TraceConfig(k=args.k)
+    n_req = args.requests
+    scene_ids, counts, seeds = synth.serving_requests(n_req, len(scenes), 1000, P)
+    offs = [int(s % (P - c + 1)) for s, c in zip(seeds, counts)]
+
+    def make(i):
+        o, c = offs[i], int(counts[i])
+        return int(scene_ids[i]), pool_o[o:o + c], pool_d[o:o + c]
+
+    # capacity: one packed launch of a large mixed batch
+    items = []
+    for j in range(6):
+        o = (j * 700_000) % (P - 700_000)
+        items.append((j % 3, pool_o[o:o + 700_000], pool_d[o:o + 700_000], alloc_result(700_000, 8, dev)))
+    trace_packed(scenes, items, cfg)
+    torch.cuda.synchronize()
+    cap_ms = _time_launches(lambda: trace_packed(scenes, items, cfg), reps=2)
+    cap = 6 * 700_000 / (cap_ms * 1e-3)
+    mean_rays = float(np.mean(counts))
+    rate = args.load * cap / mean_rays
+    arrivals = synth.poisson_arrivals(n_req, rate)
+    log(f"capacity {cap / 1e6:.1f} Mrays/s, {n_req} requests, mean {mean_rays:.0f} rays, rate {rate:.1f}/s")
+    srv = Server(scenes, cfg)
+    reqs = run_open_loop(srv, arrivals, make)
+    torch.cuda.synchronize()
+    packed = latency_stats(reqs)
+    # same results alone (bitwise) for a few requests
+    same = True
+    for r in reqs[:: max(1, n_req // 8)]:
+        a = trace(scenes[r.scene], r.ro, r.rd, cfg)
+        same &= bool(torch.equal(a.opacity, r.result.opacity) and torch.equal(a.feat, r.result.feat))
+    for r in reqs:
+        r.result = None
+    base_reqs = run_per_request(scenes, cfg, arrivals, make)
+    torch.cuda.synchronize()
+    base = latency_stats(base_reqs)
+    line = {"metric": "serving Mrays/s with p50/p99 latency (packed continuous batching vs one launch per request)",
+            "value": round(packed["mrays_s"], 3), "unit": "Mrays/s", "n_gpus": 1, "steps": n_req, "warmup": 1,
+            "ms_per_step": round(packed["mean_ms"], 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"3 resident scenes {sizes} surfels, {n_req} Poisson requests, rays "
+                                   f"log-uniform [1e3, {P}], offered load {args.load} of packed capacity, k={args.k}"},
+            "packed": packed, "per_request": base, "launches": srv.launches,
+            "capacity_mrays_s": round(cap / 1e6, 3), "mix_equals_alone": same}
+    for s in scenes:
+        s.close()
+    return line
+
+
+def run_c5(args):
+    """5M surfels, 1024^2 surface points x 32 directions (33.5M rays):
+    forward + backward, then centres += N(0, 1e-3), scales *= exp(N(0, 0.01))
+    and a refit, per step."""
+    import torch
+    from paper_2412_15867_amd import Scene, TraceConfig, trace, trace_backward, synth
+    dev = torch.device("cuda:0")
+    sc, ro, rd = gen_surface_workload(5_000_000, 1024 * 1024, 32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    params = [t(a) for a in sc.astuple()]
+    del sc
+    ro_d, rd_d = t(ro), t(rd)
+    R = ro.shape[0]
+    del ro, rd
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_STEP)
+    gO = torch.randn(R, device=dev, generator=gen)
+    gF = torch.randn((R, 8), device=dev, generator=gen)
+    gD = torch.randn(R, device=dev, generator=gen)
+    b0 = time.perf_counter()
+    scene = Scene(*params)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - b0) * 1e3
+    cfg = TraceConfig(k=args.k, recompute=args.recompute)
+    hit_cap = 0 if args.recompute else 128
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    phases = []
+    steps = args.steps
+    t0 = None
+    for i in range(args.warmup + steps):
+        if i == args.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        e = [ev() for _ in range(5)]
+        e[0].record()
+        res = trace(scene, ro_d, rd_d, cfg, hit_cap=hit_cap)
+        e[1].record()
+        grads = trace_backward(scene, ro_d, rd_d, res, gO, gF, gD, cfg=cfg)
+        e[2].record()
+        with torch.no_grad():
+            params[0].add_(torch.randn(params[0].shape, device=dev, generator=gen), alpha=1e-3)
+            params[2].mul_(torch.exp(0.01 * torch.randn(params[2].shape, device=dev, generator=gen)))
+        e[3].record()
+        scene.refit()
+        e[4].record()
+        del res, grads
+        if i >= args.warmup:
+            phases.append(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    f = [p[0].elapsed_time(p[1]) for p in phases]
+    b = [p[1].elapsed_time(p[2]) for p in phases]
+    u = [p[3].elapsed_time(p[4]) for p in phases]
+    step_ms = wall * 1e3 / steps
+    line = {"metric": "Mrays/s training-like step (fwd + bwd + perturb + refit)", "value":
+            round(R / (step_ms * 1e-3) / 1e6, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": steps,
+            "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"5000000 surfels, 1024x1024x32 = {R} MC rays, F=8, k={args.k}, "
+                                   f"{'recompute' if args.recompute else 'store'} mode"},
+            "fwd_ms": round(float(np.median(f)), 3), "bwd_ms": round(float(np.median(b)), 3),
+            "refit_ms": round(float(np.median(u)), 3), "build_ms": round(build_ms, 3)}
+    scene.close()
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "serve", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "serve", "c5"])
+    ap.add_argument("--requests", type=int, default=100)
+    ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--surfels", type=int, default=1_000_000)
     ap.add_argument("--points", type=int, default=256 * 256)
     ap.add_argument("--dirs", type=int, default=64)
@@ -226,9 +432,12 @@ def main():
         sys.exit(2)
     if args.workload == "c3":
         line = run_c3(args)
+    elif args.workload in ("c1", "c2"):
+        line = run_forward_only(args, small=args.workload == "c1")
+    elif args.workload == "serve":
+        line = run_serve(args)
     else:
-        from paper_2412_15867_amd import benchmarks
-        line = benchmarks.run(args)
+        line = run_c5(args)
     print(json.dumps(line), flush=True)
 
 
