@@ -70,10 +70,15 @@ __device__ __forceinline__ void offer(KBuf<K>& kb, const SurfelRec& s, int pos, 
 
 // Per-lane traversal stack: the first `lds_slots` entries live in LDS
 // (slot-major, so a wave's pushes hit distinct banks), deeper entries in a
-// global overflow area sized from the tree depth at build time.
+// global overflow area sized from the tree depth at build time.  The two
+// areas are typed by address space so that the LDS arm compiles to ds_*
+// instructions instead of a merged generic (flat) access.
+typedef __attribute__((address_space(3))) int lds_int;
+typedef __attribute__((address_space(1))) int glb_int;
+
 struct Stack {
-    int* lds;       // this block's LDS stack base: [lds_slots][kBlock]
-    int* ovf;       // global overflow base for slot 0 of this thread
+    lds_int* lds;   // this block's LDS stack base: [lds_slots][kBlock]
+    glb_int* ovf;   // global overflow base for slot 0 of this thread
     int ovf_stride; // distance between overflow slots
     int tid;        // thread index within the block
     int sp;
@@ -84,15 +89,19 @@ struct Stack {
         if (sp < lds_slots)
             lds[sp * kBlock + tid] = v;
         else
-            ovf[(sp - lds_slots) * ovf_stride] = v;
+            __builtin_nontemporal_store(v, ovf + (sp - lds_slots) * ovf_stride);
         ++sp;
     }
     __device__ __forceinline__ int pop()
     {
         --sp;
-        return sp < lds_slots ? lds[sp * kBlock + tid] : ovf[(sp - lds_slots) * ovf_stride];
+        if (sp < lds_slots) return lds[sp * kBlock + tid];
+        return __builtin_nontemporal_load(ovf + (sp - lds_slots) * ovf_stride);
     }
 };
+
+__device__ __forceinline__ lds_int* as_lds(int* p) { return (lds_int*)p; }
+__device__ __forceinline__ glb_int* as_glb(int* p) { return (glb_int*)p; }
 
 // One round of collection by traversal of the 4-wide tree.  Child boxes
 // are culled against the window [max(t_min, resume depth), min(t_max, K-th key)];

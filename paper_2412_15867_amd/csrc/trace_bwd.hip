@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(SceneView sc, RawSurfels ra
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
     // the re-march stack lives entirely in the global area (0 LDS slots)
-    Stack st{nullptr, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), tid, 0, 0};
+    Stack st{nullptr, as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr), tid, 0, 0};
     float4* myck = ck ? ck + gtid : nullptr;
     const GradAcc acc{hkeys, hvals, go, P.F};
     const int64_t chunks = (R + kBlock - 1) / kBlock;

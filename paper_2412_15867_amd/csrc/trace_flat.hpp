@@ -105,7 +105,7 @@ __device__ __forceinline__ void write_result(const Source& src, const LaneRay& l
 template <int K, int FM, class Source>
 __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot, const TraceParams& P, Stack& st)
 {
-    enum { kTrav = 0, kComp = 1, kFetch = 2 };
+    enum { kTrav = 0, kComp = 1, kFetch = 2, kDead = 3 };
     const float inf = __int_as_float(0x7f800000);
     int64_t slot = first_slot;
     LaneRay lr;
@@ -113,6 +113,8 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
     float ix = 0.0f, iy = 0.0f, iz = 0.0f;
     float T = 1.0f, O = 0.0f, D = 0.0f;
     float acc[FM];
+#pragma unroll
+    for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
     int nh = 0;
     uint64_t after = 0, round_last = 0;
     bool round_full = false, term = false;
@@ -122,31 +124,16 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
     kb.clear();
     Counters ct;
     while (true) {
-        if (mode == kFetch) {
-            if (!src.next(slot, lr, ray)) break;
-            T = 1.0f, O = 0.0f, D = 0.0f, nh = 0;
-#pragma unroll
-            for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
-            ct = Counters();
-            after = 0;
-            term = false;
-            kb.clear();
-            if (lr.sc.n <= 0 || !ray_valid(ray)) {
-                write_result<FM>(src, lr, O, D, T, acc, nh, ct);
-                continue;
-            }
-            ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
-            cur = 0;
-            st.sp = 0;
-            ++ct.rounds;
-            mode = kTrav;
-        }
-        if (mode == kTrav) {
-            if (cur == kItemEmpty) {
-                round_full = kb.full();
-                round_last = kb.last();
-                mode = kComp;
-            } else if (cur >= 0) {
+        // Phase vote: the wave runs, per iteration, only the kind of step the
+        // most lanes are waiting for (wave-uniform branch); the rest wait.
+        const bool want_node = mode == kTrav && cur != kItemEmpty && cur >= 0;
+        const bool want_leaf = mode == kTrav && cur < 0;
+        const bool want_other = mode != kDead && !want_node && !want_leaf;
+        const uint64_t bn = __ballot(want_node), bl = __ballot(want_leaf), bo = __ballot(want_other);
+        if ((bn | bl | bo) == 0) break;
+        const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
+        if (cn >= cl && cn >= co) {
+            if (want_node) {
                 ++ct.nodes;
                 const float4* np = reinterpret_cast<const float4*>(lr.sc.wnodes + cur);
                 const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5];
@@ -184,15 +171,41 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
                 if (key[2] < inf) st.push(ref[2]);
                 if (key[1] < inf) st.push(ref[1]);
                 cur = key[0] < inf ? ref[0] : (st.sp > 0 ? st.pop() : kItemEmpty);
-            } else {
+            }
+        } else if (cl >= co) {
+            if (want_leaf) {
                 const int first = (cur & ~kLeafBit) >> 4;
                 const int cnt = (cur & 15) + 1;
                 offer<K>(kb, load_rec(lr.sc.rec, first), first, ray, P.t_min, P.t_max, after, ct);
                 cur = cnt > 1 ? cluster_ref(first + 1, cnt - 1) : (st.sp > 0 ? st.pop() : kItemEmpty);
             }
-        }
-        if (mode == kComp) {
-            if (kb.cnt > 0 && !term) {
+        } else if (want_other) {
+            if (mode == kFetch) {
+                if (!src.next(slot, lr, ray)) {
+                    mode = kDead;
+                } else {
+                    T = 1.0f, O = 0.0f, D = 0.0f, nh = 0;
+#pragma unroll
+                    for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
+                    ct = Counters();
+                    after = 0;
+                    term = false;
+                    kb.clear();
+                    if (lr.sc.n <= 0 || !ray_valid(ray)) {
+                        write_result<FM>(src, lr, O, D, T, acc, nh, ct);
+                    } else {
+                        ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
+                        cur = 0;
+                        st.sp = 0;
+                        ++ct.rounds;
+                        mode = kTrav;
+                    }
+                }
+            } else if (mode == kTrav) {  // stack drained: the round's buffer is final
+                round_full = kb.full();
+                round_last = kb.last();
+                mode = kComp;
+            } else if (kb.cnt > 0 && !term) {
                 const int pos = kb.pos(0);
 #pragma unroll
                 for (int j = 0; j < K - 1; ++j) kb.k[j] = kb.k[j + 1];

@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, i
     __shared__ int lds_stack[BVH ? kStackLds * kBlock : 1];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
-    Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
-             0, kStackLds};
+    Stack st{as_lds(lds_stack), as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr),
+             static_cast<int>(threadIdx.x), 0, kStackLds};
     if (BVH) {
         const PlainSource src{sc, out, ro, rd, R, nthr};
         trace_flat<K, FM>(src, gtid, P, st);
@@ -160,8 +160,8 @@ __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__
     __shared__ int lds_stack[kStackLds * kBlock];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
-    Stack st{lds_stack, ovf_slots > 0 ? ovf + gtid : nullptr, static_cast<int>(nthr), static_cast<int>(threadIdx.x),
-             0, kStackLds};
+    Stack st{as_lds(lds_stack), as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr),
+             static_cast<int>(threadIdx.x), 0, kStackLds};
     const PackedSource src{scenes, items, n_items, n_rays, nthr};
     trace_flat<K, FM>(src, gtid, P, st);
 }
