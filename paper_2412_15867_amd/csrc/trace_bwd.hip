@@ -25,8 +25,12 @@ namespace irgs {
 
 namespace {
 
-constexpr int kHashSlots = 512;  // per block; a power of two
-constexpr int kHashProbes = 16;
+constexpr int kBwdBlock = 64;    // one wave per block: one table per 64 consecutive rays
+constexpr int kHashBits = 8;
+constexpr int kHashSlots = 1 << kHashBits;
+constexpr int kHashProbes = 8;
+constexpr int kHashFill = kHashSlots * 3 / 4;  // no new keys once this many slots are taken
+constexpr int kNearHits = 24;    // only a ray's first hits (shared by neighbouring rays) use the table
 constexpr int kLdsFeat = 8;      // feature gradients pre-reduced in LDS (the rest go straight to global)
 constexpr int kLdsComp = 10 + kLdsFeat;
 
@@ -45,6 +49,7 @@ struct HitGrad {
 struct GradAcc {
     int* keys;     // kHashSlots, -1 = empty
     float* vals;   // [kLdsComp][kHashSlots]
+    int* filled;   // slots taken in this chunk
     GradOut go;
     int F;
 
@@ -64,24 +69,29 @@ struct GradAcc {
     }
 
     template <int FM>
-    __device__ __forceinline__ void add(int id, const HitGrad<FM>& h) const
+    __device__ __forceinline__ void add(int id, const HitGrad<FM>& h, bool near) const
     {
-        uint32_t slot = (static_cast<uint32_t>(id) * 2654435761u) >> (32 - 9);
         int found = -1;
-        for (int p = 0; p < kHashProbes; ++p) {
-            const int k = keys[slot];
-            if (k == id) {
-                found = static_cast<int>(slot);
-                break;
-            }
-            if (k == -1) {
-                const int prev = atomicCAS(&keys[slot], -1, id);
-                if (prev == -1 || prev == id) {
+        if (near) {
+            uint32_t slot = (static_cast<uint32_t>(id) * 2654435761u) >> (32 - kHashBits);
+            const bool may_insert = *filled < kHashFill;
+            for (int p = 0; p < kHashProbes; ++p) {
+                const int k = keys[slot];
+                if (k == id) {
                     found = static_cast<int>(slot);
                     break;
                 }
+                if (k == -1) {
+                    if (!may_insert) break;
+                    const int prev = atomicCAS(&keys[slot], -1, id);
+                    if (prev == -1) atomicAdd(filled, 1);
+                    if (prev == -1 || prev == id) {
+                        found = static_cast<int>(slot);
+                        break;
+                    }
+                }
+                slot = (slot + 1) & (kHashSlots - 1);
             }
-            slot = (slot + 1) & (kHashSlots - 1);
         }
         if (found >= 0) {
 #pragma unroll
@@ -102,7 +112,7 @@ struct GradAcc {
 
     __device__ __forceinline__ void flush(int tid) const
     {
-        for (int slot = tid; slot < kHashSlots; slot += kBlock) {
+        for (int slot = tid; slot < kHashSlots; slot += kBwdBlock) {
             const int id = keys[slot];
             if (id < 0) continue;
             const int nc = 10 + (F < kLdsFeat ? F : kLdsFeat);
@@ -115,14 +125,15 @@ struct GradAcc {
 
     __device__ __forceinline__ void clear(int tid) const
     {
-        for (int i = tid; i < kHashSlots; i += kBlock) keys[i] = -1;
-        for (int i = tid; i < kLdsComp * kHashSlots; i += kBlock) vals[i] = 0.0f;
+        if (tid == 0) *filled = 0;
+        for (int i = tid; i < kHashSlots; i += kBwdBlock) keys[i] = -1;
+        for (int i = tid; i < kLdsComp * kHashSlots; i += kBwdBlock) vals[i] = 0.0f;
     }
 };
 
 template <int FM>
 __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, const Ray& ray, float Ti, float& S,
-                                         float gO, const float* gF, float gD, const GradAcc& acc)
+                                         float gO, const float* gF, float gD, const GradAcc& acc, bool near)
 {
     const int64_t i = id;
     const float mx = raw.mu[3 * i], my = raw.mu[3 * i + 1], mz = raw.mu[3 * i + 2];
@@ -192,7 +203,7 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, c
     h.g[4] = (dx - x * proj) * inv;
     h.g[5] = (dy - y * proj) * inv;
     h.g[6] = (dz - z * proj) * inv;
-    acc.add<FM>(id, h);
+    acc.add<FM>(id, h, near);
 }
 
 // alpha of the k-buffer entry at Morton position pos (the same arithmetic as
@@ -239,10 +250,17 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
     if (nh_saved == 0) return;
     float S = 0.0f;
     if (use_saved && nh_saved > 0 && nh_saved <= saved.H_cap) {
+        const int* ids = saved.hit_ids + r * saved.H_cap;
+        const float* Ts = saved.hit_T + r * saved.H_cap;
+        int id = ids[nh_saved - 1];
+        float Ti = Ts[nh_saved - 1];
         for (int h = nh_saved - 1; h >= 0; --h) {
-            const int id = saved.hit_ids[r * saved.H_cap + h];
-            const float Ti = saved.hit_T[r * saved.H_cap + h];
-            grad_hit<FM>(raw, P.F, id, ray, Ti, S, gO, gF, gD, go);
+            // fetch the next (earlier) hit while this one is processed
+            const int id_n = h > 0 ? ids[h - 1] : 0;
+            const float T_n = h > 0 ? Ts[h - 1] : 0.0f;
+            grad_hit<FM>(raw, P.F, id, ray, Ti, S, gO, gF, gD, go, h < kNearHits);
+            id = id_n;
+            Ti = T_n;
         }
         return;
     }
@@ -306,31 +324,32 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
             float Ti;
             entry<K>(kb, Tj, j, &pos, &Ti);
             const int id = __float_as_int(sc.rec[pos].c.w);
-            grad_hit<FM>(raw, P.F, id, ray, Ti, S, gO, gF, gD, go);
+            grad_hit<FM>(raw, P.F, id, ray, Ti, S, gO, gF, gD, go, nb + j < kNearHits);
         }
     }
 }
 
 template <int K, int FM>
-__global__ __launch_bounds__(kBlock) void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
+__global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                      const float* __restrict__ ro, const float* __restrict__ rd,
                                                      OutPtrs saved, bool use_saved, GradIn gin, GradOut go, int* ovf,
                                                      int ovf_slots, float4* ck)
 {
     __shared__ int hkeys[kHashSlots];
     __shared__ float hvals[kLdsComp * kHashSlots];
+    __shared__ int hfilled;
     const int tid = threadIdx.x;
-    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + tid;
-    const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
+    const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBwdBlock + tid;
+    const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBwdBlock;
     // the re-march stack lives entirely in the global area (0 LDS slots)
     Stack st{nullptr, as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr), tid, 0, 0};
     float4* myck = ck ? ck + gtid : nullptr;
-    const GradAcc acc{hkeys, hvals, go, P.F};
-    const int64_t chunks = (R + kBlock - 1) / kBlock;
+    const GradAcc acc{hkeys, hvals, &hfilled, go, P.F};
+    const int64_t chunks = (R + kBwdBlock - 1) / kBwdBlock;
     for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
         acc.clear(tid);
         __syncthreads();
-        const int64_t r = c * kBlock + tid;
+        const int64_t r = c * kBwdBlock + tid;
         if (r < R) {
             const Ray ray = load_ray(ro, rd, r);
             bwd_one<K, FM>(sc, raw, P, ray, r, saved, use_saved, gin, acc, st, myck, nthr);
@@ -347,7 +366,7 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
                      int* ovf, int ovf_slots, float* ck, hipStream_t st)
 {
     const int64_t nthr = trace_threads(R);
-    k_backward<K, FM><<<static_cast<unsigned>(nthr / kBlock), kBlock, 0, st>>>(
+    k_backward<K, FM><<<static_cast<unsigned>(nthr / kBwdBlock), kBwdBlock, 0, st>>>(
         sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, reinterpret_cast<float4*>(ck));
     return hipGetLastError();
 }
