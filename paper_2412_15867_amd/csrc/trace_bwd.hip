@@ -131,78 +131,82 @@ struct GradAcc {
     }
 };
 
+// Gradient of one hit.  The geometry and the chain rule are evaluated in
+// FP64 from the FP32 parameters: for a grazing ray (small n.r_d) FP32
+// rounding of the depth is amplified into u, v and into dtau/dmu; FP64 keeps
+// every surfel's gradient at FP32 accuracy.  Only the per-surfel
+// contributions are rounded to FP32 for accumulation.  The transmittance
+// before the hit (Ti) is the forward pass's own.
 template <int FM>
-__device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, const Ray& ray, float Ti, float& S,
+__device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, const Ray& ray, float Ti_f, float& S_f,
                                          float gO, const float* gF, float gD, const GradAcc& acc, bool near)
 {
     const int64_t i = id;
-    const float mx = raw.mu[3 * i], my = raw.mu[3 * i + 1], mz = raw.mu[3 * i + 2];
-    const float4 q = *reinterpret_cast<const float4*>(raw.quat + 4 * i);
+    const double mx = raw.mu[3 * i], my = raw.mu[3 * i + 1], mz = raw.mu[3 * i + 2];
+    const float4 qf = *reinterpret_cast<const float4*>(raw.quat + 4 * i);
     const float2 sc = *reinterpret_cast<const float2*>(raw.scale + 2 * i);
-    const float su = sc.x, sv = sc.y;
-    const float o = raw.opac[i];
-    float tu[3], tv[3], nn[3];
-    const float qn = quat_frame(q, tu, tv, nn);
-
-    const float wx = mx - ray.ox, wy = my - ray.oy, wz = mz - ray.oz;
-    const float den = dot3(nn[0], nn[1], nn[2], ray.dx, ray.dy, ray.dz);
-    const float num = dot3(nn[0], nn[1], nn[2], wx, wy, wz);
-    const float tau = num / den;
-    const float px = fmaf(tau, ray.dx, -wx), py = fmaf(tau, ray.dy, -wy), pz = fmaf(tau, ray.dz, -wz);
-    const float u = dot3(px, py, pz, tu[0], tu[1], tu[2]) / su;
-    const float v = dot3(px, py, pz, tv[0], tv[1], tv[2]) / sv;
-    const float G = __expf(-0.5f * fmaf(u, u, v * v));
-    const float alpha = o * G;
+    const double su = sc.x, sv = sc.y;
+    const double o = raw.opac[i];
+    const double qn = sqrt(double(qf.x) * qf.x + double(qf.y) * qf.y + double(qf.z) * qf.z + double(qf.w) * qf.w);
+    const double inv = 1.0 / qn;
+    const double w = qf.x * inv, x = qf.y * inv, y = qf.z * inv, z = qf.w * inv;
+    const double tu0 = 1.0 - 2.0 * (y * y + z * z), tu1 = 2.0 * (x * y + w * z), tu2 = 2.0 * (x * z - w * y);
+    const double tv0 = 2.0 * (x * y - w * z), tv1 = 1.0 - 2.0 * (x * x + z * z), tv2 = 2.0 * (y * z + w * x);
+    const double n0 = 2.0 * (x * z + w * y), n1 = 2.0 * (y * z - w * x), n2 = 1.0 - 2.0 * (x * x + y * y);
+    const double dx_ = ray.dx, dy_ = ray.dy, dz_ = ray.dz;
+    const double wx = mx - ray.ox, wy = my - ray.oy, wz = mz - ray.oz;
+    const double den = n0 * dx_ + n1 * dy_ + n2 * dz_;
+    const double tau = (n0 * wx + n1 * wy + n2 * wz) / den;
+    const double px = tau * dx_ - wx, py = tau * dy_ - wy, pz = tau * dz_ - wz;
+    const double u = (px * tu0 + py * tu1 + pz * tu2) / su;
+    const double v = (px * tv0 + py * tv1 + pz * tv2) / sv;
+    const double G = exp(-0.5 * (u * u + v * v));
+    const double alpha = o * G;
+    const double Ti = Ti_f;
+    const double S = S_f;
 
     HitGrad<FM> h;
-    float c = fmaf(gD, tau, gO);
+    double c = gO + gD * tau;
     const float* f = raw.feat + i * F;
 #pragma unroll
     for (int k = 0; k < FM; ++k) {
         const float fv = k < F ? f[k] : 0.0f;
-        c = fmaf(gF[k], fv, c);
+        c += double(gF[k]) * fv;
     }
-    const float wgt = Ti * alpha;
-    const float dA = Ti * (c - S);
-    S = fmaf(alpha, c, (1.0f - alpha) * S);
+    const double wgt = Ti * alpha;
+    const double dA = Ti * (c - S);
+    S_f = static_cast<float>(alpha * c + (1.0 - alpha) * S);
 
 #pragma unroll
-    for (int k = 0; k < FM; ++k) h.g[10 + k] = wgt * gF[k];
-    h.g[9] = dA * G;
+    for (int k = 0; k < FM; ++k) h.g[10 + k] = static_cast<float>(wgt * gF[k]);
+    h.g[9] = static_cast<float>(dA * G);
 
-    const float gu = -dA * alpha * u;
-    const float gv = -dA * alpha * v;
-    h.g[7] = -gu * u / su;
-    h.g[8] = -gv * v / sv;
+    const double gu = -dA * alpha * u;
+    const double gv = -dA * alpha * v;
+    h.g[7] = static_cast<float>(-gu * u / su);
+    h.g[8] = static_cast<float>(-gv * v / sv);
     // p - mu = tau d - w;  du/d(p-mu) = t_u / s_u
-    const float gpx = gu * tu[0] / su + gv * tv[0] / sv;
-    const float gpy = gu * tu[1] / su + gv * tv[1] / sv;
-    const float gpz = gu * tu[2] / su + gv * tv[2] / sv;
-    const float gtau = fmaf(wgt, gD, dot3(gpx, gpy, gpz, ray.dx, ray.dy, ray.dz));
-    const float gt_den = gtau / den;
-    h.g[0] = fmaf(gt_den, nn[0], -gpx);
-    h.g[1] = fmaf(gt_den, nn[1], -gpy);
-    h.g[2] = fmaf(gt_den, nn[2], -gpz);
+    const double au = gu / su, av = gv / sv;
+    const double gpx = au * tu0 + av * tv0, gpy = au * tu1 + av * tv1, gpz = au * tu2 + av * tv2;
+    const double gtau = wgt * gD + gpx * dx_ + gpy * dy_ + gpz * dz_;
+    const double gt_den = gtau / den;
+    h.g[0] = static_cast<float>(gt_den * n0 - gpx);
+    h.g[1] = static_cast<float>(gt_den * n1 - gpy);
+    h.g[2] = static_cast<float>(gt_den * n2 - gpz);
     // dtau/dn = -(p - mu) / den;  du/dt_u = (p - mu) / s_u
-    const float gn0 = -gt_den * px, gn1 = -gt_den * py, gn2 = -gt_den * pz;
-    const float au = gu / su, av = gv / sv;
-    const float gu0 = au * px, gu1 = au * py, gu2 = au * pz;
-    const float gv0 = av * px, gv1 = av * py, gv2 = av * pz;
-    const float inv = 1.0f / qn;
-    const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
+    const double gn0 = -gt_den * px, gn1 = -gt_den * py, gn2 = -gt_den * pz;
+    const double gu0 = au * px, gu1 = au * py, gu2 = au * pz;
+    const double gv0 = av * px, gv1 = av * py, gv2 = av * pz;
     // derivatives of the rotation columns with respect to (w, x, y, z)
-    const float dw = 2.0f * (z * gu1 - y * gu2 - z * gv0 + x * gv2 + y * gn0 - x * gn1);
-    const float dx = 2.0f * (y * gu1 + z * gu2 + y * gv0 - 2.0f * x * gv1 + w * gv2 + z * gn0 - w * gn1 -
-                             2.0f * x * gn2);
-    const float dy = 2.0f * (-2.0f * y * gu0 + x * gu1 - w * gu2 + x * gv0 + z * gv2 + w * gn0 + z * gn1 -
-                             2.0f * y * gn2);
-    const float dz = 2.0f * (-2.0f * z * gu0 + w * gu1 + x * gu2 - w * gv0 - 2.0f * z * gv1 + y * gv2 +
-                             x * gn0 + y * gn1);
-    const float proj = w * dw + x * dx + y * dy + z * dz;
-    h.g[3] = (dw - w * proj) * inv;
-    h.g[4] = (dx - x * proj) * inv;
-    h.g[5] = (dy - y * proj) * inv;
-    h.g[6] = (dz - z * proj) * inv;
+    const double dw = 2.0 * (z * gu1 - y * gu2 - z * gv0 + x * gv2 + y * gn0 - x * gn1);
+    const double dx = 2.0 * (y * gu1 + z * gu2 + y * gv0 - 2.0 * x * gv1 + w * gv2 + z * gn0 - w * gn1 - 2.0 * x * gn2);
+    const double dy = 2.0 * (-2.0 * y * gu0 + x * gu1 - w * gu2 + x * gv0 + z * gv2 + w * gn0 + z * gn1 - 2.0 * y * gn2);
+    const double dz = 2.0 * (-2.0 * z * gu0 + w * gu1 + x * gu2 - w * gv0 - 2.0 * z * gv1 + y * gv2 + x * gn0 + y * gn1);
+    const double proj = w * dw + x * dx + y * dy + z * dz;
+    h.g[3] = static_cast<float>((dw - w * proj) * inv);
+    h.g[4] = static_cast<float>((dx - x * proj) * inv);
+    h.g[5] = static_cast<float>((dy - y * proj) * inv);
+    h.g[6] = static_cast<float>((dz - z * proj) * inv);
     acc.add<FM>(id, h, near);
 }
 
