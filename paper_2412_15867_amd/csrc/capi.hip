@@ -256,7 +256,7 @@ size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
     const size_t thr = static_cast<size_t>(trace_threads(R));
     size_t b = thr * 64 * sizeof(int);  // worst-case stack overflow area
     if (flags & IRGS_FLAG_RECOMPUTE) b += thr * kBwdCheckpoints * 4 * sizeof(float);
-    return b;
+    return b;  // plus, for a backward, 4 * ceil32(10 + F) bytes per surfel
 }
 
 irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, irgs_scene* out)
@@ -380,7 +380,7 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
     const size_t thr = static_cast<size_t>(trace_threads(R));
     AsyncBuf ovf, ck;
     hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
-    if (e == hipSuccess) e = ck.alloc(thr * kBwdCheckpoints * 4 * sizeof(float), hs);
+    if (e == hipSuccess) e = ck.alloc(backward_scratch_words(R, s->n, s->F) * sizeof(float), hs);
     if (e != hipSuccess) return hip_fail(e, "backward scratch");
     RawSurfels raw{s->p.mu, s->p.quat, s->p.scale, s->p.opacity, s->p.feat};
     GradIn g{gin->g_opacity, gin->g_feat, gin->g_depth};

@@ -89,9 +89,15 @@ hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool u
                         hipStream_t st);
 
 // Backward.  Store mode reads saved ids and T (rays with n_hits > H_cap are
-// re-marched); recompute mode re-marches every ray.  `ck` is checkpoint
-// scratch of trace_threads(R) * kBwdCheckpoints * 4 words.
+// re-marched); recompute mode re-marches every ray.  `ck` is scratch of
+// backward_scratch_words(R, N, F) floats: re-march checkpoints, then the
+// interleaved per-surfel gradient accumulator.
 constexpr int kBwdCheckpoints = 8;
+inline int grad_stride(int F) { return ((10 + F + 31) / 32) * 32; }
+inline size_t backward_scratch_words(int64_t R, int64_t N, int F)
+{
+    return static_cast<size_t>(trace_threads(R)) * kBwdCheckpoints * 4 + static_cast<size_t>(N) * grad_stride(F);
+}
 hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int k, int64_t R,
                            const float* ro, const float* rd, const OutPtrs& saved, bool use_saved,
                            const GradIn& gin, const GradOut& gout, int* ovf, int ovf_slots, float* ck,

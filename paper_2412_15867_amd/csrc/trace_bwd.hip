@@ -50,76 +50,67 @@ struct GradAcc {
     int* keys;     // kHashSlots, -1 = empty
     float* vals;   // [kLdsComp][kHashSlots]
     int* filled;   // slots taken in this chunk
-    GradOut go;
+    float* gbuf;   // per-surfel interleaved accumulator: gbuf[id * gs + c]
+    int gs;        // stride of gbuf in floats (a multiple of 32: one 128 B line per surfel at F <= 22)
     int F;
 
-    __device__ __forceinline__ void global_add(int64_t i, int c, float v) const
+    __device__ __forceinline__ int ncomp() const { return 10 + F; }
+
+    // Direct accumulation of one hit (used by the re-march path).
+    template <int FM>
+    __device__ __forceinline__ void direct(int id, const HitGrad<FM>& h) const
     {
-        if (c < 3) {
-            if (go.mu) atomicAdd(go.mu + 3 * i + c, v);
-        } else if (c < 7) {
-            if (go.quat) atomicAdd(go.quat + 4 * i + (c - 3), v);
-        } else if (c < 9) {
-            if (go.scale) atomicAdd(go.scale + 2 * i + (c - 7), v);
-        } else if (c == 9) {
-            if (go.opac) atomicAdd(go.opac + i, v);
-        } else {
-            if (go.feat) atomicAdd(go.feat + i * F + (c - 10), v);
-        }
+        float* g = gbuf + static_cast<int64_t>(id) * gs;
+#pragma unroll
+        for (int c = 0; c < 10 + FM; ++c)
+            if (c < 10 + F && h.g[c] != 0.0f) atomicAdd(g + c, h.g[c]);
     }
 
+    // Try the LDS table; on success the components below kLdsComp are
+    // accumulated there and zeroed in h (the rest stay for the caller).
     template <int FM>
-    __device__ __forceinline__ void add(int id, const HitGrad<FM>& h, bool near) const
+    __device__ __forceinline__ bool table(int id, HitGrad<FM>& h) const
     {
+        uint32_t slot = (static_cast<uint32_t>(id) * 2654435761u) >> (32 - kHashBits);
+        const bool may_insert = *filled < kHashFill;
         int found = -1;
-        if (near) {
-            uint32_t slot = (static_cast<uint32_t>(id) * 2654435761u) >> (32 - kHashBits);
-            const bool may_insert = *filled < kHashFill;
-            for (int p = 0; p < kHashProbes; ++p) {
-                const int k = keys[slot];
-                if (k == id) {
+        for (int p = 0; p < kHashProbes; ++p) {
+            const int k = keys[slot];
+            if (k == id) {
+                found = static_cast<int>(slot);
+                break;
+            }
+            if (k == -1) {
+                if (!may_insert) break;
+                const int prev = atomicCAS(&keys[slot], -1, id);
+                if (prev == -1) atomicAdd(filled, 1);
+                if (prev == -1 || prev == id) {
                     found = static_cast<int>(slot);
                     break;
                 }
-                if (k == -1) {
-                    if (!may_insert) break;
-                    const int prev = atomicCAS(&keys[slot], -1, id);
-                    if (prev == -1) atomicAdd(filled, 1);
-                    if (prev == -1 || prev == id) {
-                        found = static_cast<int>(slot);
-                        break;
-                    }
-                }
-                slot = (slot + 1) & (kHashSlots - 1);
             }
+            slot = (slot + 1) & (kHashSlots - 1);
         }
-        if (found >= 0) {
+        if (found < 0) return false;
 #pragma unroll
-            for (int c = 0; c < 10 + FM; ++c) {
-                if (c < 10 + F) {
-                    if (c < kLdsComp)
-                        atomicAdd(vals + c * kHashSlots + found, h.g[c]);
-                    else
-                        global_add(id, c, h.g[c]);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 10 + FM; ++c)
-                if (c < 10 + F) global_add(id, c, h.g[c]);
+        for (int c = 0; c < kLdsComp && c < 10 + FM; ++c) {
+            if (c < 10 + F) atomicAdd(vals + c * kHashSlots + found, h.g[c]);
+            h.g[c] = 0.0f;
         }
+        return true;
     }
 
+    // Table to gbuf: consecutive lanes take consecutive components of one
+    // entry, so each atomic instruction touches few cache lines.
     __device__ __forceinline__ void flush(int tid) const
     {
-        for (int slot = tid; slot < kHashSlots; slot += kBwdBlock) {
+        const int nc = 10 + (F < kLdsFeat ? F : kLdsFeat);
+        for (int flat = tid; flat < kHashSlots * nc; flat += kBwdBlock) {
+            const int slot = flat / nc, c = flat - slot * nc;
             const int id = keys[slot];
             if (id < 0) continue;
-            const int nc = 10 + (F < kLdsFeat ? F : kLdsFeat);
-            for (int c = 0; c < nc; ++c) {
-                const float v = vals[c * kHashSlots + slot];
-                if (v != 0.0f) global_add(id, c, v);
-            }
+            const float v = vals[c * kHashSlots + slot];
+            if (v != 0.0f) atomicAdd(gbuf + static_cast<int64_t>(id) * gs + c, v);
         }
     }
 
@@ -139,7 +130,7 @@ struct GradAcc {
 // before the hit (Ti) is the forward pass's own.
 template <int FM>
 __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, const Ray& ray, float Ti_f, float& S_f,
-                                         float gO, const float* gF, float gD, const GradAcc& acc, bool near)
+                                         float gO, const float* gF, float gD, HitGrad<FM>& h)
 {
     const int64_t i = id;
     const double mx = raw.mu[3 * i], my = raw.mu[3 * i + 1], mz = raw.mu[3 * i + 2];
@@ -165,7 +156,6 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, c
     const double Ti = Ti_f;
     const double S = S_f;
 
-    HitGrad<FM> h;
     double c = gO + gD * tau;
     const float* f = raw.feat + i * F;
 #pragma unroll
@@ -207,7 +197,6 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, c
     h.g[4] = static_cast<float>((dx - x * proj) * inv);
     h.g[5] = static_cast<float>((dy - y * proj) * inv);
     h.g[6] = static_cast<float>((dz - z * proj) * inv);
-    acc.add<FM>(id, h, near);
 }
 
 // alpha of the k-buffer entry at Morton position pos (the same arithmetic as
@@ -234,41 +223,36 @@ __device__ __forceinline__ void entry(const KBuf<K>& kb, const float* Tj, int j,
     *T = rt;
 }
 
-template <int K, int FM>
-__device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
-                                        const Ray& ray, int64_t r, const OutPtrs& saved, bool use_saved,
-                                        const GradIn& gin, const GradAcc& go, Stack& st, float4* ck,
-                                        int64_t ck_stride)
+template <int FM>
+struct LaneUp {
+    float gO, gD, gF[FM];
+    bool any;
+};
+
+template <int FM>
+__device__ __forceinline__ LaneUp<FM> load_upstream(const GradIn& gin, int64_t r, int F)
 {
-    const float gO = gin.gO ? gin.gO[r] : 0.0f;
-    const float gD = gin.gD ? gin.gD[r] : 0.0f;
-    float gF[FM];
-    bool any = gO != 0.0f || gD != 0.0f;
+    LaneUp<FM> u;
+    u.gO = gin.gO ? gin.gO[r] : 0.0f;
+    u.gD = gin.gD ? gin.gD[r] : 0.0f;
+    u.any = u.gO != 0.0f || u.gD != 0.0f;
 #pragma unroll
     for (int k = 0; k < FM; ++k) {
-        gF[k] = (gin.gF && k < P.F) ? gin.gF[r * P.F + k] : 0.0f;
-        any = any || gF[k] != 0.0f;
+        u.gF[k] = (gin.gF && k < F) ? gin.gF[r * F + k] : 0.0f;
+        u.any = u.any || u.gF[k] != 0.0f;
     }
-    if (!any || sc.n <= 0 || !ray_valid(ray)) return;
-    const int nh_saved = saved.n_hits ? saved.n_hits[r] : -1;
-    if (nh_saved == 0) return;
+    return u;
+}
+
+// Re-march one ray (no saved list, or more hits than were saved): pass 1
+// records the state at the start of each round, pass 2 re-collects the
+// rounds last to first and walks each back to front.
+template <int K, int FM>
+__device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
+                                            const Ray& ray, const LaneUp<FM>& up, const GradAcc& acc, Stack& st,
+                                            float4* ck, int64_t ck_stride)
+{
     float S = 0.0f;
-    if (use_saved && nh_saved > 0 && nh_saved <= saved.H_cap) {
-        const int* ids = saved.hit_ids + r * saved.H_cap;
-        const float* Ts = saved.hit_T + r * saved.H_cap;
-        int id = ids[nh_saved - 1];
-        float Ti = Ts[nh_saved - 1];
-        for (int h = nh_saved - 1; h >= 0; --h) {
-            // fetch the next (earlier) hit while this one is processed
-            const int id_n = h > 0 ? ids[h - 1] : 0;
-            const float T_n = h > 0 ? Ts[h - 1] : 0.0f;
-            grad_hit<FM>(raw, P.F, id, ray, Ti, S, gO, gF, gD, go, h < kNearHits);
-            id = id_n;
-            Ti = T_n;
-        }
-        return;
-    }
-    // ---- re-march: pass 1 records the state at the start of each round
     Counters ct;
     const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
     uint64_t after = 0;
@@ -298,7 +282,6 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
         ++rounds;
     }
     const int total = nh;
-    // ---- pass 2: rounds last to first, each walked back to front
     for (int rr = rounds - 1; rr >= 0; --rr) {
         const int base = rr < kBwdCheckpoints ? rr : kBwdCheckpoints - 1;
         float4 c4 = ck[base * ck_stride];
@@ -328,39 +311,117 @@ __device__ __forceinline__ void bwd_one(const SceneView& sc, const RawSurfels& r
             float Ti;
             entry<K>(kb, Tj, j, &pos, &Ti);
             const int id = __float_as_int(sc.rec[pos].c.w);
-            grad_hit<FM>(raw, P.F, id, ray, Ti, S, gO, gF, gD, go, nb + j < kNearHits);
+            HitGrad<FM> h;
+            grad_hit<FM>(raw, P.F, id, ray, Ti, S, up.gO, up.gF, up.gD, h);
+            acc.direct<FM>(id, h);
         }
     }
 }
 
 template <int K, int FM>
 __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
-                                                     const float* __restrict__ ro, const float* __restrict__ rd,
-                                                     OutPtrs saved, bool use_saved, GradIn gin, GradOut go, int* ovf,
-                                                     int ovf_slots, float4* ck)
+                                                        const float* __restrict__ ro, const float* __restrict__ rd,
+                                                        OutPtrs saved, bool use_saved, GradIn gin, float* gbuf,
+                                                        int gs, int* ovf, int ovf_slots, float4* ck)
 {
     __shared__ int hkeys[kHashSlots];
     __shared__ float hvals[kLdsComp * kHashSlots];
     __shared__ int hfilled;
+    __shared__ int stage_id[kBwdBlock];
+    __shared__ float stage[(10 + FM) * kBwdBlock];
     const int tid = threadIdx.x;
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBwdBlock + tid;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBwdBlock;
     // the re-march stack lives entirely in the global area (0 LDS slots)
     Stack st{nullptr, as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr), tid, 0, 0};
     float4* myck = ck ? ck + gtid : nullptr;
-    const GradAcc acc{hkeys, hvals, &hfilled, go, P.F};
+    const GradAcc acc{hkeys, hvals, &hfilled, gbuf, gs, P.F};
+    const int nc = 10 + P.F;
     const int64_t chunks = (R + kBwdBlock - 1) / kBwdBlock;
     for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
         acc.clear(tid);
         __syncthreads();
         const int64_t r = c * kBwdBlock + tid;
+        Ray ray{};
+        LaneUp<FM> up{};
+        int nh = 0;
+        bool stored = false;
         if (r < R) {
-            const Ray ray = load_ray(ro, rd, r);
-            bwd_one<K, FM>(sc, raw, P, ray, r, saved, use_saved, gin, acc, st, myck, nthr);
+            ray = load_ray(ro, rd, r);
+            up = load_upstream<FM>(gin, r, P.F);
+            const int nh_saved = saved.n_hits ? saved.n_hits[r] : -1;
+            if (up.any && sc.n > 0 && ray_valid(ray) && nh_saved != 0) {
+                if (use_saved && nh_saved > 0 && nh_saved <= saved.H_cap) {
+                    stored = true;
+                    nh = nh_saved;
+                } else {
+                    bwd_remarch<K, FM>(sc, raw, P, ray, up, acc, st, myck, nthr);
+                }
+            }
+        }
+        // Saved lists: all lanes step together, back to front, so that the
+        // wave can hand every hit's gradient to the scatter below.
+        int hmax = nh;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) hmax = max(hmax, __shfl_xor(hmax, off));
+        const int* ids = saved.hit_ids + (stored ? r * saved.H_cap : 0);
+        const float* Ts = saved.hit_T + (stored ? r * saved.H_cap : 0);
+        float S = 0.0f;
+        for (int step = 0; step < hmax; ++step) {
+            const int h = nh - 1 - step;
+            const bool valid = stored && h >= 0;
+            HitGrad<FM> hg;
+            int id = -1;
+            if (valid) {
+                id = ids[h];
+                grad_hit<FM>(raw, P.F, id, ray, Ts[h], S, up.gO, up.gF, up.gD, hg);
+                if (h < kNearHits) acc.table<FM>(id, hg);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 10 + FM; ++k) hg.g[k] = 0.0f;
+            }
+            stage_id[tid] = id;
+#pragma unroll
+            for (int k = 0; k < 10 + FM; ++k) stage[k * kBwdBlock + tid] = hg.g[k];
+            __syncthreads();
+            // Transposed scatter: lane l takes component (q*64 + l) % nc of
+            // hit (q*64 + l) / nc, so consecutive lanes add consecutive
+            // components of one surfel -- a few cache lines per instruction.
+            for (int flat = tid; flat < kBwdBlock * nc; flat += kBwdBlock) {
+                const int hit = flat / nc, comp = flat - hit * nc;
+                const int sid = stage_id[hit];
+                const float v = stage[comp * kBwdBlock + hit];
+                if (sid >= 0 && v != 0.0f) atomicAdd(gbuf + static_cast<int64_t>(sid) * gs + comp, v);
+            }
+            __syncthreads();
         }
         __syncthreads();
         acc.flush(tid);
         __syncthreads();
+    }
+}
+
+// gbuf (interleaved per surfel) added into the caller's gradient arrays.
+__global__ void k_grad_out(int64_t n, int F, int gs, const float* __restrict__ gbuf, GradOut go)
+{
+    const int nc = 10 + F;
+    for (int64_t flat = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; flat < n * nc;
+         flat += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t i = flat / nc;
+        const int c = static_cast<int>(flat - i * nc);
+        const float v = gbuf[i * gs + c];
+        if (v == 0.0f) continue;
+        if (c < 3) {
+            if (go.mu) go.mu[3 * i + c] += v;
+        } else if (c < 7) {
+            if (go.quat) go.quat[4 * i + c - 3] += v;
+        } else if (c < 9) {
+            if (go.scale) go.scale[2 * i + c - 7] += v;
+        } else if (c == 9) {
+            if (go.opac) go.opac[i] += v;
+        } else {
+            if (go.feat) go.feat[i * F + c - 10] += v;
+        }
     }
 }
 
@@ -370,8 +431,17 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
                      int* ovf, int ovf_slots, float* ck, hipStream_t st)
 {
     const int64_t nthr = trace_threads(R);
+    const int gs = grad_stride(P.F);
+    float* gbuf = ck + static_cast<size_t>(nthr) * kBwdCheckpoints * 4;
+    hipError_t e = fill_u32(gbuf, static_cast<int64_t>(sc.n) * gs, 0u, st);
+    if (e != hipSuccess) return e;
     k_backward<K, FM><<<static_cast<unsigned>(nthr / kBwdBlock), kBwdBlock, 0, st>>>(
-        sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, reinterpret_cast<float4*>(ck));
+        sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf, gs, ovf, ovf_slots, reinterpret_cast<float4*>(ck));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t work = static_cast<int64_t>(sc.n) * (10 + P.F);
+    const int blocks = static_cast<int>(work < 2048 * 256 ? (work + 255) / 256 : 2048);
+    k_grad_out<<<blocks > 0 ? blocks : 1, 256, 0, st>>>(sc.n, P.F, gs, gbuf, go);
     return hipGetLastError();
 }
 
