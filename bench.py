@@ -63,11 +63,15 @@ def cpu_baseline(sc, ro, rd, gO, gF, gD, budget_s: float = 12.0):
     from oracle import grad as ograd
     threads = oracle.max_threads()
     g = np.random.default_rng(7)
-    probe = np.sort(g.choice(ro.shape[0], 32, replace=False))
-    t0 = time.perf_counter()
-    oracle.trace(sc.astuple(), ro[probe], rd[probe], hit_cap=8)
-    per_ray = (time.perf_counter() - t0) / probe.size
-    n = int(max(64, min(65536, budget_s / max(per_ray, 1e-9))))
+    # per-ray cost from two probe sizes (each call also pays a fixed per-surfel setup)
+    tp = []
+    for m in (64, 320):
+        probe = np.sort(g.choice(ro.shape[0], m, replace=False))
+        t0 = time.perf_counter()
+        oracle.trace(sc.astuple(), ro[probe], rd[probe], hit_cap=8)
+        tp.append(time.perf_counter() - t0)
+    per_ray = max((tp[1] - tp[0]) / 256, 1e-9)
+    n = int(max(256, min(65536, budget_s / per_ray)))
     idx = np.sort(g.choice(ro.shape[0], n, replace=False))
     t0 = time.perf_counter()
     r = oracle.trace(sc.astuple(), ro[idx], rd[idx], hit_cap=512)
