@@ -254,7 +254,7 @@ size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
     (void)F;
     if (R <= 0) return 0;
     const size_t thr = static_cast<size_t>(trace_threads(R));
-    size_t b = thr * 64 * sizeof(int);  // worst-case stack overflow area
+    size_t b = thr * (64 + 2 * kDeferCap) * sizeof(int);  // worst-case stack overflow + deferred lists
     if (flags & IRGS_FLAG_RECOMPUTE) b += thr * kBwdCheckpoints * 4 * sizeof(float);
     return b;  // plus, for a backward, 4 * ceil32(10 + F) bytes per surfel
 }
@@ -357,11 +357,13 @@ irgs_status irgs_trace(irgs_scene s, const irgs_params* p, int64_t R, const floa
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const bool bvh = !(p->flags & IRGS_FLAG_BRUTE_FORCE);
     const int slots = bvh ? ovf_slots_of(s) : 0;
-    AsyncBuf ovf;
-    hipError_t e = ovf.alloc(static_cast<size_t>(trace_threads(R)) * slots * sizeof(int), hs);
+    AsyncBuf ovf, dq;
+    const size_t thr = static_cast<size_t>(trace_threads(R));
+    hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
+    if (e == hipSuccess && bvh) e = dq.alloc(thr * 2 * kDeferCap * sizeof(int), hs);
     if (e != hipSuccess) return hip_fail(e, "trace scratch");
     e = launch_trace(view_of(s), trace_params(p, s->F), p->k, bvh, R, ro, rd, out_ptrs(out),
-                     static_cast<int*>(ovf.p), slots, hs);
+                     static_cast<int*>(ovf.p), slots, static_cast<int*>(dq.p), hs);
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return IRGS_OK;
 }
@@ -438,24 +440,22 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
     const size_t thr = static_cast<size_t>(grid) * kBlock;
     const size_t vb = sizeof(SceneView) * n_scenes, wb = sizeof(WorkItem) * n_items;
     const size_t items_off = (vb + 63) / 64 * 64;
-    const size_t counter_off = (items_off + wb + 63) / 64 * 64;
-    AsyncBuf meta, ovf;
-    hipError_t e = meta.alloc(counter_off + 64, hs);
+    AsyncBuf meta, ovf, dq;
+    hipError_t e = meta.alloc(items_off + wb, hs);
     if (e == hipSuccess) e = ovf.alloc(thr * slots * sizeof(int), hs);
+    if (e == hipSuccess) e = dq.alloc(thr * 2 * kDeferCap * sizeof(int), hs);
     if (e != hipSuccess) return hip_fail(e, "packed scratch");
     char* base = static_cast<char*>(meta.p);
     SceneView* dviews = reinterpret_cast<SceneView*>(base);
     WorkItem* ditems = reinterpret_cast<WorkItem*>(base + items_off);
-    int* counter = reinterpret_cast<int*>(base + counter_off);
     // Pageable host sources: the copies are staged before hipMemcpyAsync
     // returns, so the vectors may go out of scope afterwards.
     e = hipMemcpyAsync(dviews, views.data(), vb, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(ditems, w.data(), wb, hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = fill_u32(counter, 1, 0u, hs);
     if (e == hipSuccess) {
         TraceParams tp = trace_params(p, Fmax);
-        e = launch_packed(dviews, ditems, n_items, chunks, tp, p->k, static_cast<int*>(ovf.p), slots, counter, grid,
-                          hs);
+        e = launch_packed(dviews, ditems, n_items, chunks, tp, p->k, static_cast<int*>(ovf.p), slots,
+                          static_cast<int*>(dq.p), grid, hs);
     }
     if (e != hipSuccess) return hip_fail(e, "packed launch");
     return IRGS_OK;

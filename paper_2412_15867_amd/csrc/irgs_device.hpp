@@ -184,6 +184,19 @@ __device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, 
     return tn <= tf;
 }
 
+// Entry and exit distance of a ray in a box, clamped to [lo, hi]; the box is
+// crossed inside the window when *tn <= *tf.  Same arithmetic as box_hit.
+__device__ __forceinline__ void box_span(float lx, float ly, float lz, float hx, float hy, float hz, float ox,
+                                         float oy, float oz, float ix, float iy, float iz, float lo, float hi,
+                                         float* tn, float* tf)
+{
+    float t0x = (lx - ox) * ix, t1x = (hx - ox) * ix;
+    float t0y = (ly - oy) * iy, t1y = (hy - oy) * iy;
+    float t0z = (lz - oz) * iz, t1z = (hz - oz) * iz;
+    *tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), lo));
+    *tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), hi));
+}
+
 __device__ __forceinline__ float safe_inv(float d)
 {
     const float tiny = 1e-20f;

@@ -83,9 +83,11 @@ int64_t trace_threads(int64_t R);
 
 // Forward trace.  use_bvh = false tests every record (the plain tracer).
 // `ovf` is the global stack overflow area: ovf_slots entries per thread of
-// the grid (trace_threads(R) threads), or null when ovf_slots == 0.
+// the grid (trace_threads(R) threads), or null when ovf_slots == 0.  `dbuf`
+// holds the per-thread deferred-work lists: 2 * kDeferCap ints per thread.
+constexpr int kDeferCap = 192;
 hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,
-                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots,
+                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf,
                         hipStream_t st);
 
 // Backward.  Store mode reads saved ids and T (rays with n_hits > H_cap are
@@ -117,8 +119,8 @@ struct WorkItem {
     OutPtrs out;
 };
 
-hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_chunks,
-                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* queue_counter, int grid_blocks,
+hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_rays,
+                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* dbuf, int grid_blocks,
                          hipStream_t st);
 
 // Fill n 32-bit words with v (a kernel, so it can be captured in a graph).

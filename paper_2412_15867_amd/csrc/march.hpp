@@ -39,8 +39,9 @@ struct KBuf {
     __device__ __forceinline__ uint64_t last() const { return k[K - 1]; }
     __device__ __forceinline__ int pos(int j) const { return key_pos(k[j]); }
 
-    // Insert a key; the largest falls off the end when full.
-    __device__ __forceinline__ void insert(uint64_t key)
+    // Insert a key; the largest falls off the end when full and is returned
+    // (kKeyNone when nothing fell off).
+    __device__ __forceinline__ uint64_t insert(uint64_t key)
     {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -50,8 +51,27 @@ struct KBuf {
             key = t;
         }
         cnt = cnt < K ? cnt + 1 : K;
+        return key;
     }
 };
+
+// Offer with the outcome reported, for the deferred-work traversal:
+// returns 0 (not a hit, or at/below the resume key), 1 (inserted; *evicted
+// is the key that fell off, or kKeyNone) or 2 (a hit beyond the K-th key).
+template <int K>
+__device__ __forceinline__ int offer_ex(KBuf<K>& kb, const SurfelRec& s, int pos, const Ray& ray, float t_min,
+                                        float t_max, uint64_t after, Counters& ct, uint64_t* evicted)
+{
+    ++ct.tests;
+    float tau, rho2;
+    if (!hit_test(s, ray, t_min, t_max, &tau, &rho2)) return 0;
+    const uint64_t key = hit_key(tau, pos);
+    if (key <= after) return 0;
+    if (key >= kb.last()) return 2;
+    ++ct.inserts;
+    *evicted = kb.insert(key);
+    return 1;
+}
 
 // Offer the record at Morton position `pos` to the buffer: Eq. 6-7 test,
 // above the resume key, below the K-th key once full.

@@ -102,8 +102,45 @@ __device__ __forceinline__ void write_result(const Source& src, const LaneRay& l
         reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
 }
 
+// Per-lane deferred work carried from one k-buffer round to the next: the
+// children culled only because they start beyond the round's K-th key, the
+// hits found beyond it, and the keys pushed out of the buffer.  Every hit
+// after the round's last key lies in exactly one of them, so the next round
+// starts from this list instead of the root.  Two halves (this round's input,
+// next round's output); an overflowing output falls back to a root restart.
+struct Deferred {
+    glb_int* base;  // 2 * cap entries of this lane
+    int cap;
+    int half;       // half holding this round's input
+    int n_in, i_in, n_out;
+
+    __device__ __forceinline__ void reset()
+    {
+        half = 0;
+        n_in = i_in = n_out = 0;
+    }
+    __device__ __forceinline__ void put(int item)
+    {
+        if (n_out < cap) base[(half ^ 1) * cap + n_out] = item;
+        ++n_out;
+    }
+    __device__ __forceinline__ int take() { return base[half * cap + i_in++]; }
+    __device__ __forceinline__ bool has() const { return i_in < n_in; }
+    // Next round: consume what this one deferred; false = it overflowed.
+    __device__ __forceinline__ bool flip()
+    {
+        const bool ok = n_out <= cap;
+        half ^= 1;
+        n_in = ok ? n_out : 0;
+        i_in = 0;
+        n_out = 0;
+        return ok;
+    }
+};
+
 template <int K, int FM, class Source>
-__device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot, const TraceParams& P, Stack& st)
+__device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot, const TraceParams& P, Stack& st,
+                                           Deferred dq)
 {
     enum { kTrav = 0, kComp = 1, kFetch = 2, kDead = 3 };
     const float inf = __int_as_float(0x7f800000);
@@ -123,6 +160,11 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
     KBuf<K> kb;
     kb.clear();
     Counters ct;
+    auto next_item = [&]() -> int {
+        if (st.sp > 0) return st.pop();
+        if (dq.has()) return dq.take();
+        return kItemEmpty;
+    };
     while (true) {
         // Phase vote: the wave runs, per iteration, only the kind of step the
         // most lanes are waiting for (wave-uniform branch); the rest wait.
@@ -141,17 +183,23 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
                 const float lo = after == 0 ? P.t_min : fmaxf(P.t_min, key_tau(after));
                 const float tmax_c = fminf(P.t_max, 3.0e38f);
                 const float hi = kb.full() ? fminf(key_tau(kb.last()), tmax_c) : tmax_c;
-                float key[4];
+                float key[4], tn[4], tf[4];
                 int ref[4] = {ch.x, ch.y, ch.z, ch.w};
-                float te;
-                key[0] = box_hit(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
-                             ? te : inf;
-                key[1] = box_hit(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
-                             ? te : inf;
-                key[2] = box_hit(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
-                             ? te : inf;
-                key[3] = box_hit(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te)
-                             ? te : inf;
+                box_span(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[0],
+                         &tf[0]);
+                box_span(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[1],
+                         &tf[1]);
+                box_span(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[2],
+                         &tf[2]);
+                box_span(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[3],
+                         &tf[3]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const bool crossed = ref[c] != kNoChild && tn[c] <= tf[c];
+                    const bool inside = crossed && tn[c] <= hi;
+                    if (crossed && !inside) dq.put(ref[c]);  // beyond this round's K-th key
+                    key[c] = inside ? tn[c] : inf;
+                }
 #define IRGS_CSWAP(a, b)                    \
     if (key[b] < key[a]) {                  \
         const float tk = key[a];            \
@@ -170,14 +218,20 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
                 if (key[3] < inf) st.push(ref[3]);
                 if (key[2] < inf) st.push(ref[2]);
                 if (key[1] < inf) st.push(ref[1]);
-                cur = key[0] < inf ? ref[0] : (st.sp > 0 ? st.pop() : kItemEmpty);
+                cur = key[0] < inf ? ref[0] : next_item();
             }
         } else if (cl >= co) {
             if (want_leaf) {
                 const int first = (cur & ~kLeafBit) >> 4;
                 const int cnt = (cur & 15) + 1;
-                offer<K>(kb, load_rec(lr.sc.rec, first), first, ray, P.t_min, P.t_max, after, ct);
-                cur = cnt > 1 ? cluster_ref(first + 1, cnt - 1) : (st.sp > 0 ? st.pop() : kItemEmpty);
+                uint64_t ev = kKeyNone;
+                const int res = offer_ex<K>(kb, load_rec(lr.sc.rec, first), first, ray, P.t_min, P.t_max, after, ct,
+                                            &ev);
+                if (res == 2)
+                    dq.put(cluster_ref(first, 1));
+                else if (res == 1 && ev != kKeyNone)
+                    dq.put(cluster_ref(key_pos(ev), 1));
+                cur = cnt > 1 ? cluster_ref(first + 1, cnt - 1) : next_item();
             }
         } else if (want_other) {
             if (mode == kFetch) {
@@ -191,6 +245,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
                     after = 0;
                     term = false;
                     kb.clear();
+                    dq.reset();
                     if (lr.sc.n <= 0 || !ray_valid(ray)) {
                         write_result<FM>(src, lr, O, D, T, acc, nh, ct);
                     } else {
@@ -201,7 +256,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
                         mode = kTrav;
                     }
                 }
-            } else if (mode == kTrav) {  // stack drained: the round's buffer is final
+            } else if (mode == kTrav) {  // stack and deferred input drained: the buffer is final
                 round_full = kb.full();
                 round_last = kb.last();
                 mode = kComp;
@@ -237,9 +292,9 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
             } else {
                 after = round_last;
                 kb.clear();
-                cur = 0;
                 st.sp = 0;
                 ++ct.rounds;
+                cur = dq.flip() ? next_item() : 0;  // deferred list, or the root after an overflow
                 mode = kTrav;
             }
         }

@@ -91,7 +91,7 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
 template <int K, int FM, bool BVH>
 __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, int64_t R,
                                                   const float* __restrict__ ro, const float* __restrict__ rd,
-                                                  OutPtrs out, int* ovf, int ovf_slots)
+                                                  OutPtrs out, int* ovf, int ovf_slots, int* dbuf, int dcap)
 {
     __shared__ int lds_stack[BVH ? kStackLds * kBlock : 1];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -100,7 +100,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, i
              static_cast<int>(threadIdx.x), 0, kStackLds};
     if (BVH) {
         const PlainSource src{sc, out, ro, rd, R, nthr};
-        trace_flat<K, FM>(src, gtid, P, st);
+        Deferred dq{as_glb(dbuf + gtid * 2 * dcap), dcap, 0, 0, 0, 0};
+        trace_flat<K, FM>(src, gtid, P, st, dq);
     } else {
         for (int64_t r = gtid; r < R; r += nthr) {
             const Ray ray = load_ray(ro, rd, r);
@@ -111,51 +112,51 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, i
 
 template <int K, int FM, bool BVH>
 hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
-                     const OutPtrs& out, int* ovf, int ovf_slots, hipStream_t st)
+                     const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf, int dcap, hipStream_t st)
 {
     const int64_t nthr = trace_threads(R);
     k_trace<K, FM, BVH><<<static_cast<unsigned>(nthr / kBlock), kBlock, 0, st>>>(sc, P, R, ro, rd, out, ovf,
-                                                                                 ovf_slots);
+                                                                                 ovf_slots, dbuf, dcap);
     return hipGetLastError();
 }
 
 template <int K, bool BVH>
 hipError_t launch_k(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
-                    const OutPtrs& out, int* ovf, int ovf_slots, hipStream_t st)
+                    const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf, int dcap, hipStream_t st)
 {
-    if (P.F <= 4) return launch_kf<K, 4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-    if (P.F <= 8) return launch_kf<K, 8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+    if (P.F <= 4) return launch_kf<K, 4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+    if (P.F <= 8) return launch_kf<K, 8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
     if constexpr (K == 16 || K == 32) {
-        if (P.F <= 16) return launch_kf<K, 16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-        if (P.F <= 64) return launch_kf<K, 64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        if (P.F <= 16) return launch_kf<K, 16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        if (P.F <= 64) return launch_kf<K, 64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <bool BVH>
 hipError_t launch_b(const SceneView& sc, const TraceParams& P, int k, int64_t R, const float* ro, const float* rd,
-                    const OutPtrs& out, int* ovf, int ovf_slots, hipStream_t st)
+                    const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf, int dcap, hipStream_t st)
 {
     switch (k) {
-        case 1: return launch_k<1, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-        case 2: return launch_k<2, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-        case 4: return launch_k<4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-        case 8: return launch_k<8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-        case 16: return launch_k<16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-        case 32: return launch_k<32, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
-        case 64: return launch_k<64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, st);
+        case 1: return launch_k<1, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        case 2: return launch_k<2, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        case 4: return launch_k<4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        case 8: return launch_k<8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        case 16: return launch_k<16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        case 32: return launch_k<32, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        case 64: return launch_k<64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-// Packed persistent launch: every block repeatedly takes the next chunk of
-// kBlock rays from a device counter; a chunk belongs to one work item (one
-// request of one scene), so different requests and scenes share a launch.
-// The loop ends for every block once the counter passes n_chunks.
+// Packed persistent launch: the lanes of the grid stride over the
+// concatenation of every work item's rays (an item is one request on one
+// scene), so different requests and scenes share one launch.
 template <int K, int FM>
 __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__ scenes,
                                                    const WorkItem* __restrict__ items, int n_items,
-                                                   int64_t n_rays, TraceParams P, int* ovf, int ovf_slots)
+                                                   int64_t n_rays, TraceParams P, int* ovf, int ovf_slots,
+                                                   int* dbuf, int dcap)
 {
     __shared__ int lds_stack[kStackLds * kBlock];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -163,48 +164,49 @@ __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__
     Stack st{as_lds(lds_stack), as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr),
              static_cast<int>(threadIdx.x), 0, kStackLds};
     const PackedSource src{scenes, items, n_items, n_rays, nthr};
-    trace_flat<K, FM>(src, gtid, P, st);
+    Deferred dq{as_glb(dbuf + gtid * 2 * dcap), dcap, 0, 0, 0, 0};
+    trace_flat<K, FM>(src, gtid, P, st, dq);
 }
 
 template <int K, int FM>
-hipError_t launch_packed_kf(const SceneView* scenes, const WorkItem* items, int n_items, int64_t n_chunks,
-                            const TraceParams& P, int* ovf, int ovf_slots, int* counter, int grid_blocks,
+hipError_t launch_packed_kf(const SceneView* scenes, const WorkItem* items, int n_items, int64_t n_rays,
+                            const TraceParams& P, int* ovf, int ovf_slots, int* dbuf, int grid_blocks,
                             hipStream_t st)
 {
-    (void)counter;
-    k_packed<K, FM><<<grid_blocks, kBlock, 0, st>>>(scenes, items, n_items, n_chunks, P, ovf, ovf_slots);
+    k_packed<K, FM><<<grid_blocks, kBlock, 0, st>>>(scenes, items, n_items, n_rays, P, ovf, ovf_slots, dbuf,
+                                                    kDeferCap);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_chunks,
-                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* queue_counter, int grid_blocks,
+hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_rays,
+                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* dbuf, int grid_blocks,
                          hipStream_t st)
 {
-    if (n_chunks <= 0 || n_items <= 0) return hipSuccess;
+    if (n_rays <= 0 || n_items <= 0) return hipSuccess;
     if (k == 16 && P.F <= 8)
-        return launch_packed_kf<16, 8>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+        return launch_packed_kf<16, 8>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
                                        grid_blocks, st);
     if (k == 16 && P.F <= 64)
-        return launch_packed_kf<16, 64>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+        return launch_packed_kf<16, 64>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
                                         grid_blocks, st);
     if (k == 32 && P.F <= 8)
-        return launch_packed_kf<32, 8>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+        return launch_packed_kf<32, 8>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
                                        grid_blocks, st);
     if (k == 32 && P.F <= 64)
-        return launch_packed_kf<32, 64>(scenes_dev, items_dev, n_items, n_chunks, P, ovf, ovf_slots, queue_counter,
+        return launch_packed_kf<32, 64>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
                                         grid_blocks, st);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,
-                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots,
+                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf,
                         hipStream_t st)
 {
     if (R <= 0) return hipSuccess;
-    return use_bvh ? launch_b<true>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, st)
-                   : launch_b<false>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, st);
+    return use_bvh ? launch_b<true>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, dbuf, kDeferCap, st)
+                   : launch_b<false>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, dbuf, kDeferCap, st);
 }
 
 }  // namespace irgs
