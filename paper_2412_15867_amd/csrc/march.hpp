@@ -39,39 +39,26 @@ struct KBuf {
     __device__ __forceinline__ uint64_t last() const { return k[K - 1]; }
     __device__ __forceinline__ int pos(int j) const { return key_pos(k[j]); }
 
-    // Insert a key; the largest falls off the end when full and is returned
-    // (kKeyNone when nothing fell off).
-    __device__ __forceinline__ uint64_t insert(uint64_t key)
+    // Insert `key` when `ins` holds (then key is below the last entry; keys
+    // are unique); the last entry falls off the end and is returned
+    // (kKeyNone when nothing fell off).  Branch-free: every comparison is
+    // against the new key, so they are independent; then, from the back, an
+    // entry takes its predecessor when the key sorts before the predecessor,
+    // else the key when it sorts before the entry.  With ins false nothing
+    // moves.
+    __device__ __forceinline__ uint64_t insert_if(bool ins, uint64_t key)
     {
+        bool lt[K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const bool lt = key < k[j];
-            const uint64_t t = lt ? k[j] : key;
-            k[j] = lt ? key : k[j];
-            key = t;
-        }
-        cnt = cnt < K ? cnt + 1 : K;
-        return key;
+        for (int j = 0; j < K; ++j) lt[j] = ins && key < k[j];
+        const uint64_t out = ins ? k[K - 1] : kKeyNone;
+#pragma unroll
+        for (int j = K - 1; j > 0; --j) k[j] = lt[j - 1] ? k[j - 1] : (lt[j] ? key : k[j]);  // lt[j-1] implies lt[j]
+        k[0] = lt[0] ? key : k[0];
+        cnt += (ins && cnt < K) ? 1 : 0;
+        return out;
     }
 };
-
-// Offer with the outcome reported, for the deferred-work traversal:
-// returns 0 (not a hit, or at/below the resume key), 1 (inserted; *evicted
-// is the key that fell off, or kKeyNone) or 2 (a hit beyond the K-th key).
-template <int K>
-__device__ __forceinline__ int offer_ex(KBuf<K>& kb, const SurfelRec& s, int pos, const Ray& ray, float t_min,
-                                        float t_max, uint64_t after, Counters& ct, uint64_t* evicted)
-{
-    ++ct.tests;
-    float tau, rho2;
-    if (!hit_test(s, ray, t_min, t_max, &tau, &rho2)) return 0;
-    const uint64_t key = hit_key(tau, pos);
-    if (key <= after) return 0;
-    if (key >= kb.last()) return 2;
-    ++ct.inserts;
-    *evicted = kb.insert(key);
-    return 1;
-}
 
 // Offer the record at Morton position `pos` to the buffer: Eq. 6-7 test,
 // above the resume key, below the K-th key once full.
@@ -85,7 +72,7 @@ __device__ __forceinline__ void offer(KBuf<K>& kb, const SurfelRec& s, int pos, 
     const uint64_t key = hit_key(tau, pos);
     if (key <= after || key >= kb.last()) return;
     ++ct.inserts;
-    kb.insert(key);
+    kb.insert_if(true, key);
 }
 
 // Per-lane traversal stack: the first `lds_slots` entries live in LDS

@@ -195,7 +195,8 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
                          &tf[3]);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const bool crossed = ref[c] != kNoChild && tn[c] <= tf[c];
+                    // an empty slot has an all +inf box, which is never crossed
+                    const bool crossed = tn[c] <= tf[c];
                     const bool inside = crossed && tn[c] <= hi;
                     if (crossed && !inside) dq.put(ref[c]);  // beyond this round's K-th key
                     key[c] = inside ? tn[c] : inf;
@@ -221,18 +222,25 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
                 cur = key[0] < inf ? ref[0] : next_item();
             }
         } else if (cl >= co) {
+            // Test one surfel; the buffer insert runs outside the divergent
+            // region (predicated), so the buffer needs no per-branch copy.
+            bool ins = false;
+            uint64_t key = kKeyNone;
             if (want_leaf) {
                 const int first = (cur & ~kLeafBit) >> 4;
                 const int cnt = (cur & 15) + 1;
-                uint64_t ev = kKeyNone;
-                const int res = offer_ex<K>(kb, load_rec(lr.sc.rec, first), first, ray, P.t_min, P.t_max, after, ct,
-                                            &ev);
-                if (res == 2)
-                    dq.put(cluster_ref(first, 1));
-                else if (res == 1 && ev != kKeyNone)
-                    dq.put(cluster_ref(key_pos(ev), 1));
+                ++ct.tests;
+                float tau, rho2;
+                const bool hit = hit_test(load_rec(lr.sc.rec, first), ray, P.t_min, P.t_max, &tau, &rho2);
+                key = hit_key(tau, first);
+                const bool above = hit && key > after;
+                ins = above && key < kb.last();
+                if (above && !ins) dq.put(cluster_ref(first, 1));  // beyond this round's K-th key
                 cur = cnt > 1 ? cluster_ref(first + 1, cnt - 1) : next_item();
             }
+            ct.inserts += ins ? 1 : 0;
+            const uint64_t ev = kb.insert_if(ins, key);
+            if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
         } else if (want_other) {
             if (mode == kFetch) {
                 if (!src.next(slot, lr, ray)) {
