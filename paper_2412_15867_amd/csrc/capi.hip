@@ -159,6 +159,18 @@ int ovf_slots_of(irgs_scene s)
     return extra > 0 ? extra : 0;
 }
 
+// Forward scratch: the ray-claim counter heads the deferred-list buffer.
+constexpr size_t kClaimBytes = 256;
+FlatScratch flat_scratch(void* ovf, int slots, void* dq)
+{
+    FlatScratch f{};
+    f.ovf = static_cast<int*>(ovf);
+    f.ovf_slots = slots;
+    f.next_ray = static_cast<unsigned long long*>(dq);
+    f.dbuf = dq ? reinterpret_cast<int*>(static_cast<char*>(dq) + kClaimBytes) : nullptr;
+    return f;
+}
+
 OutPtrs out_ptrs(const irgs_out* o)
 {
     OutPtrs r{};
@@ -254,7 +266,7 @@ size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
     (void)F;
     if (R <= 0) return 0;
     const size_t thr = static_cast<size_t>(trace_threads(R));
-    size_t b = thr * (64 + 2 * kDeferCap) * sizeof(int);  // worst-case stack overflow + deferred lists
+    size_t b = thr * (64 + 2 * kDeferCap) * sizeof(int) + kClaimBytes;  // stack overflow, deferred lists
     if (flags & IRGS_FLAG_RECOMPUTE) b += thr * kBwdCheckpoints * 4 * sizeof(float);
     return b;  // plus, for a backward, 4 * ceil32(10 + F) bytes per surfel
 }
@@ -360,10 +372,10 @@ irgs_status irgs_trace(irgs_scene s, const irgs_params* p, int64_t R, const floa
     AsyncBuf ovf, dq;
     const size_t thr = static_cast<size_t>(trace_threads(R));
     hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
-    if (e == hipSuccess && bvh) e = dq.alloc(thr * 2 * kDeferCap * sizeof(int), hs);
+    if (e == hipSuccess && bvh) e = dq.alloc(kClaimBytes + thr * 2 * kDeferCap * sizeof(int), hs);
     if (e != hipSuccess) return hip_fail(e, "trace scratch");
     e = launch_trace(view_of(s), trace_params(p, s->F), p->k, bvh, R, ro, rd, out_ptrs(out),
-                     static_cast<int*>(ovf.p), slots, static_cast<int*>(dq.p), hs);
+                     flat_scratch(ovf.p, slots, dq.p), hs);
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return IRGS_OK;
 }
@@ -443,7 +455,7 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
     AsyncBuf meta, ovf, dq;
     hipError_t e = meta.alloc(items_off + wb, hs);
     if (e == hipSuccess) e = ovf.alloc(thr * slots * sizeof(int), hs);
-    if (e == hipSuccess) e = dq.alloc(thr * 2 * kDeferCap * sizeof(int), hs);
+    if (e == hipSuccess) e = dq.alloc(kClaimBytes + thr * 2 * kDeferCap * sizeof(int), hs);
     if (e != hipSuccess) return hip_fail(e, "packed scratch");
     char* base = static_cast<char*>(meta.p);
     SceneView* dviews = reinterpret_cast<SceneView*>(base);
@@ -454,8 +466,7 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
     if (e == hipSuccess) e = hipMemcpyAsync(ditems, w.data(), wb, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) {
         TraceParams tp = trace_params(p, Fmax);
-        e = launch_packed(dviews, ditems, n_items, chunks, tp, p->k, static_cast<int*>(ovf.p), slots,
-                          static_cast<int*>(dq.p), grid, hs);
+        e = launch_packed(dviews, ditems, n_items, chunks, tp, p->k, flat_scratch(ovf.p, slots, dq.p), grid, hs);
     }
     if (e != hipSuccess) return hip_fail(e, "packed launch");
     return IRGS_OK;

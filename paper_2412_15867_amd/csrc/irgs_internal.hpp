@@ -81,13 +81,19 @@ constexpr int kMaxF = 64;
 // Number of persistent trace threads launched for R rays (grid-stride).
 int64_t trace_threads(int64_t R);
 
-// Forward trace.  use_bvh = false tests every record (the plain tracer).
-// `ovf` is the global stack overflow area: ovf_slots entries per thread of
-// the grid (trace_threads(R) threads), or null when ovf_slots == 0.  `dbuf`
-// holds the per-thread deferred-work lists: 2 * kDeferCap ints per thread.
+// Device scratch of a persistent forward launch, sized for trace_threads(R)
+// threads (the launch may use fewer).
 constexpr int kDeferCap = 192;
+struct FlatScratch {
+    int* ovf;                      // stack overflow: ovf_slots ints per thread, or null when ovf_slots == 0
+    int ovf_slots;
+    int* dbuf;                     // deferred-work lists: 2 * kDeferCap ints per thread (BVH launches)
+    unsigned long long* next_ray;  // ray-claim counter (BVH launches); the launch zeroes it
+};
+
+// Forward trace.  use_bvh = false tests every record (the plain tracer).
 hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,
-                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf,
+                        const float* ro, const float* rd, const OutPtrs& out, const FlatScratch& fs,
                         hipStream_t st);
 
 // Backward.  Store mode reads saved ids and T (rays with n_hits > H_cap are
@@ -120,8 +126,7 @@ struct WorkItem {
 };
 
 hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_rays,
-                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* dbuf, int grid_blocks,
-                         hipStream_t st);
+                         const TraceParams& P, int k, const FlatScratch& fs, int grid_blocks, hipStream_t st);
 
 // Fill n 32-bit words with v (a kernel, so it can be captured in a graph).
 hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);

@@ -11,7 +11,8 @@
 //         an empty stack ends the round;
 //   COMP  composite the nearest buffered hit (Eq. 2: w = T alpha, T *= 1 - a)
 //         or, with the buffer drained, start the next round or finish the ray;
-//   FETCH take the lane's next ray.
+//   FETCH claim the lane's next ray from a global counter (rays go to lanes
+//         as lanes free up, so the launch drains evenly).
 // Per ray the arithmetic and its order are exactly those of the nested form,
 // so results are bit-identical; only the interleaving across lanes changes.
 #pragma once
@@ -30,38 +31,35 @@ struct LaneRay {
     SceneView sc;
 };
 
-// One scene, rays [0, R), lane g takes rays g, g + stride, ...
+// One scene, rays [0, R).
 struct PlainSource {
     SceneView sc;
     OutPtrs o;
     const float* ro;
     const float* rd;
     int64_t R;
-    int64_t stride;
 
-    __device__ __forceinline__ bool next(int64_t& slot, LaneRay& lr, Ray& ray) const
+    __device__ __forceinline__ bool load(int64_t slot, LaneRay& lr, Ray& ray) const
     {
         if (slot >= R) return false;
         lr.r = slot;
         lr.item = 0;
         lr.sc = sc;
         ray = load_ray(ro, rd, slot);
-        slot += stride;
         return true;
     }
     __device__ __forceinline__ const OutPtrs& out(const LaneRay&) const { return o; }
 };
 
-// Several requests over several scenes: a lane's slot indexes the
-// concatenation of the items' rays; the owning item is found by bisection.
+// Several requests over several scenes: a slot indexes the concatenation of
+// the items' rays; the owning item is found by bisection.
 struct PackedSource {
     const SceneView* scenes;
     const WorkItem* items;
     int n_items;
     int64_t total;
-    int64_t stride;
 
-    __device__ __forceinline__ bool next(int64_t& slot, LaneRay& lr, Ray& ray) const
+    __device__ __forceinline__ bool load(int64_t slot, LaneRay& lr, Ray& ray) const
     {
         if (slot >= total) return false;
         int lo = 0, hi = n_items - 1;
@@ -78,11 +76,24 @@ struct PackedSource {
         lr.item = lo;
         lr.sc = scenes[it.scene];
         ray = load_ray(it.ro, it.rd, lr.r);
-        slot += stride;
         return true;
     }
     __device__ __forceinline__ const OutPtrs& out(const LaneRay& lr) const { return items[lr.item].out; }
 };
+
+// Claim one slot per calling lane from a global counter: one atomic per
+// wave, slots in lane order (consecutive lanes get consecutive rays).  Call
+// with exactly the lanes that need a slot active.
+__device__ __forceinline__ int64_t claim_slot(unsigned long long* next)
+{
+    const uint64_t need = __ballot(1);
+    const int rank = __popcll(need & __lanemask_lt());
+    const int leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
+    unsigned long long base = 0;
+    if (rank == 0) base = atomicAdd(next, static_cast<unsigned long long>(__popcll(need)));
+    base = __shfl(base, leader);
+    return static_cast<int64_t>(base) + rank;
+}
 
 template <int FM, class Source>
 __device__ __forceinline__ void write_result(const Source& src, const LaneRay& lr, float O, float D, float T,
@@ -139,12 +150,11 @@ struct Deferred {
 };
 
 template <int K, int FM, class Source>
-__device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot, const TraceParams& P, Stack& st,
-                                           Deferred dq)
+__device__ __forceinline__ void trace_flat(const Source& src, unsigned long long* next_ray, const TraceParams& P,
+                                           Stack& st, Deferred dq)
 {
     enum { kTrav = 0, kComp = 1, kFetch = 2, kDead = 3 };
     const float inf = __int_as_float(0x7f800000);
-    int64_t slot = first_slot;
     LaneRay lr;
     Ray ray;
     float ix = 0.0f, iy = 0.0f, iz = 0.0f;
@@ -243,7 +253,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, int64_t first_slot
             if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
         } else if (want_other) {
             if (mode == kFetch) {
-                if (!src.next(slot, lr, ray)) {
+                if (!src.load(claim_slot(next_ray), lr, ray)) {
                     mode = kDead;
                 } else {
                     T = 1.0f, O = 0.0f, D = 0.0f, nh = 0;

@@ -26,6 +26,24 @@ int64_t trace_threads(int64_t R)
 
 namespace {
 
+// Blocks of `kern` (kBlock threads each) that the whole device keeps
+// resident at once, or 0 if the runtime cannot say.  Persistent launches use
+// at most this many, so no block waits for another to finish.
+template <class Kern>
+int64_t resident_blocks(Kern kern)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess) return 0;
+    return per_cu > 0 && cus > 0 ? static_cast<int64_t>(per_cu) * cus : 0;
+}
+
+inline unsigned persistent_grid(int64_t max_blocks, int64_t resident)
+{
+    return static_cast<unsigned>(resident > 0 && resident < max_blocks ? resident : max_blocks);
+}
+
 template <int K, int FM, bool BVH>
 __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams& P, const Ray& ray, int64_t r,
                                           const OutPtrs& out, Stack& st)
@@ -91,17 +109,17 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
 template <int K, int FM, bool BVH>
 __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, int64_t R,
                                                   const float* __restrict__ ro, const float* __restrict__ rd,
-                                                  OutPtrs out, int* ovf, int ovf_slots, int* dbuf, int dcap)
+                                                  OutPtrs out, FlatScratch fs)
 {
     __shared__ int lds_stack[BVH ? kStackLds * kBlock : 1];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
-    Stack st{as_lds(lds_stack), as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr),
+    Stack st{as_lds(lds_stack), as_glb(fs.ovf_slots > 0 ? fs.ovf + gtid : nullptr), static_cast<int>(nthr),
              static_cast<int>(threadIdx.x), 0, kStackLds};
     if (BVH) {
-        const PlainSource src{sc, out, ro, rd, R, nthr};
-        Deferred dq{as_glb(dbuf + gtid * 2 * dcap), dcap, 0, 0, 0, 0};
-        trace_flat<K, FM>(src, gtid, P, st, dq);
+        const PlainSource src{sc, out, ro, rd, R};
+        Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
+        trace_flat<K, FM>(src, fs.next_ray, P, st, dq);
     } else {
         for (int64_t r = gtid; r < R; r += nthr) {
             const Ray ray = load_ray(ro, rd, r);
@@ -112,101 +130,96 @@ __global__ __launch_bounds__(kBlock) void k_trace(SceneView sc, TraceParams P, i
 
 template <int K, int FM, bool BVH>
 hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
-                     const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf, int dcap, hipStream_t st)
+                     const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
 {
-    const int64_t nthr = trace_threads(R);
-    k_trace<K, FM, BVH><<<static_cast<unsigned>(nthr / kBlock), kBlock, 0, st>>>(sc, P, R, ro, rd, out, ovf,
-                                                                                 ovf_slots, dbuf, dcap);
+    if (BVH) {
+        const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
+        if (e != hipSuccess) return e;
+    }
+    const unsigned grid = persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH>));
+    k_trace<K, FM, BVH><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, fs);
     return hipGetLastError();
 }
 
 template <int K, bool BVH>
 hipError_t launch_k(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
-                    const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf, int dcap, hipStream_t st)
+                    const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
 {
-    if (P.F <= 4) return launch_kf<K, 4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-    if (P.F <= 8) return launch_kf<K, 8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+    if (P.F <= 4) return launch_kf<K, 4, BVH>(sc, P, R, ro, rd, out, fs, st);
+    if (P.F <= 8) return launch_kf<K, 8, BVH>(sc, P, R, ro, rd, out, fs, st);
     if constexpr (K == 16 || K == 32) {
-        if (P.F <= 16) return launch_kf<K, 16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-        if (P.F <= 64) return launch_kf<K, 64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        if (P.F <= 16) return launch_kf<K, 16, BVH>(sc, P, R, ro, rd, out, fs, st);
+        if (P.F <= 64) return launch_kf<K, 64, BVH>(sc, P, R, ro, rd, out, fs, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <bool BVH>
 hipError_t launch_b(const SceneView& sc, const TraceParams& P, int k, int64_t R, const float* ro, const float* rd,
-                    const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf, int dcap, hipStream_t st)
+                    const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
 {
     switch (k) {
-        case 1: return launch_k<1, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-        case 2: return launch_k<2, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-        case 4: return launch_k<4, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-        case 8: return launch_k<8, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-        case 16: return launch_k<16, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-        case 32: return launch_k<32, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
-        case 64: return launch_k<64, BVH>(sc, P, R, ro, rd, out, ovf, ovf_slots, dbuf, dcap, st);
+        case 1: return launch_k<1, BVH>(sc, P, R, ro, rd, out, fs, st);
+        case 2: return launch_k<2, BVH>(sc, P, R, ro, rd, out, fs, st);
+        case 4: return launch_k<4, BVH>(sc, P, R, ro, rd, out, fs, st);
+        case 8: return launch_k<8, BVH>(sc, P, R, ro, rd, out, fs, st);
+        case 16: return launch_k<16, BVH>(sc, P, R, ro, rd, out, fs, st);
+        case 32: return launch_k<32, BVH>(sc, P, R, ro, rd, out, fs, st);
+        case 64: return launch_k<64, BVH>(sc, P, R, ro, rd, out, fs, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-// Packed persistent launch: the lanes of the grid stride over the
-// concatenation of every work item's rays (an item is one request on one
-// scene), so different requests and scenes share one launch.
+// Packed persistent launch: lanes claim slots of the concatenation of every
+// work item's rays (an item is one request on one scene), so different
+// requests and scenes share one launch.
 template <int K, int FM>
 __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__ scenes,
                                                    const WorkItem* __restrict__ items, int n_items,
-                                                   int64_t n_rays, TraceParams P, int* ovf, int ovf_slots,
-                                                   int* dbuf, int dcap)
+                                                   int64_t n_rays, TraceParams P, FlatScratch fs)
 {
     __shared__ int lds_stack[kStackLds * kBlock];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
-    Stack st{as_lds(lds_stack), as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr),
+    Stack st{as_lds(lds_stack), as_glb(fs.ovf_slots > 0 ? fs.ovf + gtid : nullptr), static_cast<int>(nthr),
              static_cast<int>(threadIdx.x), 0, kStackLds};
-    const PackedSource src{scenes, items, n_items, n_rays, nthr};
-    Deferred dq{as_glb(dbuf + gtid * 2 * dcap), dcap, 0, 0, 0, 0};
-    trace_flat<K, FM>(src, gtid, P, st, dq);
+    const PackedSource src{scenes, items, n_items, n_rays};
+    Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
+    trace_flat<K, FM>(src, fs.next_ray, P, st, dq);
 }
 
 template <int K, int FM>
 hipError_t launch_packed_kf(const SceneView* scenes, const WorkItem* items, int n_items, int64_t n_rays,
-                            const TraceParams& P, int* ovf, int ovf_slots, int* dbuf, int grid_blocks,
-                            hipStream_t st)
+                            const TraceParams& P, const FlatScratch& fs, int grid_blocks, hipStream_t st)
 {
-    k_packed<K, FM><<<grid_blocks, kBlock, 0, st>>>(scenes, items, n_items, n_rays, P, ovf, ovf_slots, dbuf,
-                                                    kDeferCap);
+    const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
+    if (e != hipSuccess) return e;
+    const unsigned grid = persistent_grid(grid_blocks, resident_blocks(k_packed<K, FM>));
+    k_packed<K, FM><<<grid, kBlock, 0, st>>>(scenes, items, n_items, n_rays, P, fs);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_rays,
-                         const TraceParams& P, int k, int* ovf, int ovf_slots, int* dbuf, int grid_blocks,
-                         hipStream_t st)
+                         const TraceParams& P, int k, const FlatScratch& fs, int grid_blocks, hipStream_t st)
 {
     if (n_rays <= 0 || n_items <= 0) return hipSuccess;
-    if (k == 16 && P.F <= 8)
-        return launch_packed_kf<16, 8>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
-                                       grid_blocks, st);
+    if (k == 16 && P.F <= 8) return launch_packed_kf<16, 8>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
     if (k == 16 && P.F <= 64)
-        return launch_packed_kf<16, 64>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
-                                        grid_blocks, st);
-    if (k == 32 && P.F <= 8)
-        return launch_packed_kf<32, 8>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
-                                       grid_blocks, st);
+        return launch_packed_kf<16, 64>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
+    if (k == 32 && P.F <= 8) return launch_packed_kf<32, 8>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
     if (k == 32 && P.F <= 64)
-        return launch_packed_kf<32, 64>(scenes_dev, items_dev, n_items, n_rays, P, ovf, ovf_slots, dbuf,
-                                        grid_blocks, st);
+        return launch_packed_kf<32, 64>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,
-                        const float* ro, const float* rd, const OutPtrs& out, int* ovf, int ovf_slots, int* dbuf,
+                        const float* ro, const float* rd, const OutPtrs& out, const FlatScratch& fs,
                         hipStream_t st)
 {
     if (R <= 0) return hipSuccess;
-    return use_bvh ? launch_b<true>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, dbuf, kDeferCap, st)
-                   : launch_b<false>(sc, P, k, R, ro, rd, out, ovf, ovf_slots, dbuf, kDeferCap, st);
+    return use_bvh ? launch_b<true>(sc, P, k, R, ro, rd, out, fs, st) : launch_b<false>(sc, P, k, R, ro, rd, out, fs, st);
 }
 
 }  // namespace irgs
