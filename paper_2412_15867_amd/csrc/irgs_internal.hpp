@@ -78,8 +78,27 @@ struct RawSurfels {
 constexpr int kMaxK = 64;
 constexpr int kMaxF = 64;
 
-// Number of persistent trace threads launched for R rays (grid-stride).
+// Upper bound on the persistent trace threads of a launch over R rays;
+// scratch is sized per thread of this bound.
 int64_t trace_threads(int64_t R);
+
+// Blocks of `kern` (block_size threads each) that the whole device keeps
+// resident at once, or 0 if the runtime cannot say.  Persistent launches use
+// at most this many, so no block waits for another to finish.
+template <class Kern>
+int64_t resident_blocks(Kern kern, int block_size)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block_size, 0) != hipSuccess) return 0;
+    return per_cu > 0 && cus > 0 ? static_cast<int64_t>(per_cu) * cus : 0;
+}
+
+inline unsigned persistent_grid(int64_t max_blocks, int64_t resident)
+{
+    return static_cast<unsigned>(resident > 0 && resident < max_blocks ? resident : max_blocks);
+}
 
 // Device scratch of a persistent forward launch, sized for trace_threads(R)
 // threads (the launch may use fewer).
@@ -98,13 +117,15 @@ hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool u
 
 // Backward.  Store mode reads saved ids and T (rays with n_hits > H_cap are
 // re-marched); recompute mode re-marches every ray.  `ck` is scratch of
-// backward_scratch_words(R, N, F) floats: re-march checkpoints, then the
-// interleaved per-surfel gradient accumulator.
+// backward_scratch_words(R, N, F) floats: re-march checkpoints, the
+// interleaved per-surfel gradient accumulator, then a chunk-claim counter.
 constexpr int kBwdCheckpoints = 8;
+constexpr int kBwdClaimWords = 64;
 inline int grad_stride(int F) { return ((10 + F + 31) / 32) * 32; }
 inline size_t backward_scratch_words(int64_t R, int64_t N, int F)
 {
-    return static_cast<size_t>(trace_threads(R)) * kBwdCheckpoints * 4 + static_cast<size_t>(N) * grad_stride(F);
+    return static_cast<size_t>(trace_threads(R)) * kBwdCheckpoints * 4 + static_cast<size_t>(N) * grad_stride(F) +
+           kBwdClaimWords;
 }
 hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int k, int64_t R,
                            const float* ro, const float* rd, const OutPtrs& saved, bool use_saved,

@@ -322,11 +322,13 @@ template <int K, int FM>
 __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                         const float* __restrict__ ro, const float* __restrict__ rd,
                                                         OutPtrs saved, bool use_saved, GradIn gin, float* gbuf,
-                                                        int gs, int* ovf, int ovf_slots, float4* ck)
+                                                        int gs, int* ovf, int ovf_slots, float4* ck,
+                                                        unsigned long long* next_chunk)
 {
     __shared__ int hkeys[kHashSlots];
     __shared__ float hvals[kLdsComp * kHashSlots];
     __shared__ int hfilled;
+    __shared__ long long claimed;
     __shared__ int stage_id[kBwdBlock];
     __shared__ float stage[(10 + FM) * kBwdBlock];
     const int tid = threadIdx.x;
@@ -338,9 +340,14 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
     const GradAcc acc{hkeys, hvals, &hfilled, gbuf, gs, P.F};
     const int nc = 10 + P.F;
     const int64_t chunks = (R + kBwdBlock - 1) / kBwdBlock;
-    for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    // chunks of kBwdBlock rays are claimed from a global counter as blocks
+    // free up, so the launch drains evenly
+    while (true) {
+        if (tid == 0) claimed = static_cast<long long>(atomicAdd(next_chunk, 1ull));
         acc.clear(tid);
         __syncthreads();
+        const int64_t c = claimed;
+        if (c >= chunks) break;
         const int64_t r = c * kBwdBlock + tid;
         Ray ray{};
         LaneUp<FM> up{};
@@ -433,10 +440,14 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
     const int64_t nthr = trace_threads(R);
     const int gs = grad_stride(P.F);
     float* gbuf = ck + static_cast<size_t>(nthr) * kBwdCheckpoints * 4;
-    hipError_t e = fill_u32(gbuf, static_cast<int64_t>(sc.n) * gs, 0u, st);
+    unsigned long long* next_chunk =
+        reinterpret_cast<unsigned long long*>(gbuf + static_cast<size_t>(sc.n) * gs);
+    // zero the accumulator and the claim counter behind it
+    hipError_t e = fill_u32(gbuf, static_cast<int64_t>(sc.n) * gs + kBwdClaimWords, 0u, st);
     if (e != hipSuccess) return e;
-    k_backward<K, FM><<<static_cast<unsigned>(nthr / kBwdBlock), kBwdBlock, 0, st>>>(
-        sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf, gs, ovf, ovf_slots, reinterpret_cast<float4*>(ck));
+    const unsigned grid = persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM>, kBwdBlock));
+    k_backward<K, FM><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf, gs, ovf,
+                                                  ovf_slots, reinterpret_cast<float4*>(ck), next_chunk);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t work = static_cast<int64_t>(sc.n) * (10 + P.F);

@@ -26,24 +26,6 @@ int64_t trace_threads(int64_t R)
 
 namespace {
 
-// Blocks of `kern` (kBlock threads each) that the whole device keeps
-// resident at once, or 0 if the runtime cannot say.  Persistent launches use
-// at most this many, so no block waits for another to finish.
-template <class Kern>
-int64_t resident_blocks(Kern kern)
-{
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess) return 0;
-    return per_cu > 0 && cus > 0 ? static_cast<int64_t>(per_cu) * cus : 0;
-}
-
-inline unsigned persistent_grid(int64_t max_blocks, int64_t resident)
-{
-    return static_cast<unsigned>(resident > 0 && resident < max_blocks ? resident : max_blocks);
-}
-
 template <int K, int FM, bool BVH>
 __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams& P, const Ray& ray, int64_t r,
                                           const OutPtrs& out, Stack& st)
@@ -136,7 +118,7 @@ hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const
         const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
         if (e != hipSuccess) return e;
     }
-    const unsigned grid = persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH>));
+    const unsigned grid = persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH>, kBlock));
     k_trace<K, FM, BVH><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, fs);
     return hipGetLastError();
 }
@@ -194,7 +176,7 @@ hipError_t launch_packed_kf(const SceneView* scenes, const WorkItem* items, int 
 {
     const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
     if (e != hipSuccess) return e;
-    const unsigned grid = persistent_grid(grid_blocks, resident_blocks(k_packed<K, FM>));
+    const unsigned grid = persistent_grid(grid_blocks, resident_blocks(k_packed<K, FM>, kBlock));
     k_packed<K, FM><<<grid, kBlock, 0, st>>>(scenes, items, n_items, n_rays, P, fs);
     return hipGetLastError();
 }
