@@ -26,9 +26,9 @@ constexpr int kItemEmpty = 0x7fffffff;  // no current item (stack drained)
 
 // Where a lane's rays come from and where their results go.
 struct LaneRay {
-    int64_t r;  // ray index within its output arrays
-    int item;   // work item (packed launches), 0 otherwise
-    SceneView sc;
+    int64_t r;     // ray index within its output arrays
+    int item;      // work item (packed launches), 0 otherwise
+    SceneView sc;  // the item's scene (packed launches only)
 };
 
 // One scene, rays [0, R).
@@ -44,11 +44,12 @@ struct PlainSource {
         if (slot >= R) return false;
         lr.r = slot;
         lr.item = 0;
-        lr.sc = sc;
         ray = load_ray(ro, rd, slot);
         return true;
     }
     __device__ __forceinline__ const OutPtrs& out(const LaneRay&) const { return o; }
+    // the one scene of the launch (uniform: kept out of per-lane registers)
+    __device__ __forceinline__ const SceneView& view(const LaneRay&) const { return sc; }
 };
 
 // Several requests over several scenes: a slot indexes the concatenation of
@@ -79,6 +80,7 @@ struct PackedSource {
         return true;
     }
     __device__ __forceinline__ const OutPtrs& out(const LaneRay& lr) const { return items[lr.item].out; }
+    __device__ __forceinline__ const SceneView& view(const LaneRay& lr) const { return lr.sc; }
 };
 
 // Claim one slot per calling lane from a global counter: one atomic per
@@ -101,7 +103,7 @@ __device__ __forceinline__ void write_result(const Source& src, const LaneRay& l
 {
     const OutPtrs& out = src.out(lr);
     const int64_t r = lr.r;
-    const int F = lr.sc.F;
+    const int F = src.view(lr).F;
     out.O[r] = O;
     out.D[r] = D;
 #pragma unroll
@@ -187,7 +189,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         if (cn >= cl && cn >= co) {
             if (want_node) {
                 ++ct.nodes;
-                const float4* np = reinterpret_cast<const float4*>(lr.sc.wnodes + cur);
+                const float4* np = reinterpret_cast<const float4*>(src.view(lr).wnodes + cur);
                 const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5];
                 const int4 ch = reinterpret_cast<const int4*>(np)[6];
                 const float lo = after == 0 ? P.t_min : fmaxf(P.t_min, key_tau(after));
@@ -241,7 +243,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const int cnt = (cur & 15) + 1;
                 ++ct.tests;
                 float tau, rho2;
-                const bool hit = hit_test(load_rec(lr.sc.rec, first), ray, P.t_min, P.t_max, &tau, &rho2);
+                const bool hit = hit_test(load_rec(src.view(lr).rec, first), ray, P.t_min, P.t_max, &tau, &rho2);
                 key = hit_key(tau, first);
                 const bool above = hit && key > after;
                 ins = above && key < kb.last();
@@ -264,7 +266,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     term = false;
                     kb.clear();
                     dq.reset();
-                    if (lr.sc.n <= 0 || !ray_valid(ray)) {
+                    if (src.view(lr).n <= 0 || !ray_valid(ray)) {
                         write_result<FM>(src, lr, O, D, T, acc, nh, ct);
                     } else {
                         ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
@@ -284,7 +286,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 for (int j = 0; j < K - 1; ++j) kb.k[j] = kb.k[j + 1];
                 kb.k[K - 1] = kKeyNone;
                 --kb.cnt;
-                const SurfelRec s = load_rec(lr.sc.rec, pos);
+                const SurfelRec s = load_rec(src.view(lr).rec, pos);
                 float tau, rho2;
                 plane_hit(s, ray, &tau, &rho2);
                 const float a = alpha_of(s, rho2);
@@ -292,10 +294,10 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const float w = T * a;
                 O += w;
                 D = fmaf(w, tau, D);
-                const float* f = lr.sc.feat + static_cast<int64_t>(id) * lr.sc.F;
+                const float* f = src.view(lr).feat + static_cast<int64_t>(id) * src.view(lr).F;
 #pragma unroll
                 for (int c = 0; c < FM; ++c)
-                    if (c < lr.sc.F) acc[c] = fmaf(w, f[c], acc[c]);
+                    if (c < src.view(lr).F) acc[c] = fmaf(w, f[c], acc[c]);
                 const OutPtrs& out = src.out(lr);
                 if (out.hit_ids && nh < out.H_cap) {
                     out.hit_ids[lr.r * out.H_cap + nh] = id;
