@@ -165,6 +165,15 @@ __device__ __forceinline__ int key_pos(uint64_t k) { return static_cast<int>(sta
 
 constexpr uint64_t kKeyNone = ~0ull;  // larger than every key
 
+// Slab tests take the ray as (inverse direction i, no = -o * i) so that each
+// slab distance is one fma: (l - o) / d == l * i + no.  The fused form
+// rounds differently from (l - o) * i by less than an ulp of o * i, far
+// inside the padding every leaf box carries (at least 1e-5 (1 + |mu|) per
+// axis), so a box never loses a hit it contains.
+struct SlabRay {
+    float ix, iy, iz, nox, noy, noz;
+};
+
 // Slab test of a ray against a box, returning the entry distance; the box is
 // accepted when it overlaps [lo, hi] along the ray.  `hi` must be finite.
 // An empty box is stored with every coordinate = +inf, which this test
@@ -172,27 +181,25 @@ constexpr uint64_t kKeyNone = ~0ull;  // larger than every key
 // pushes the entry to +inf, and with all inverse directions negative the
 // exit drops to -inf).
 __device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, float hy, float hz,
-                                        float ox, float oy, float oz, float ix, float iy, float iz, float lo,
-                                        float hi, float* t_enter)
+                                        const SlabRay& q, float lo, float hi, float* t_enter)
 {
-    float t0x = (lx - ox) * ix, t1x = (hx - ox) * ix;
-    float t0y = (ly - oy) * iy, t1y = (hy - oy) * iy;
-    float t0z = (lz - oz) * iz, t1z = (hz - oz) * iz;
-    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), lo));
-    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), hi));
+    const float t0x = fmaf(lx, q.ix, q.nox), t1x = fmaf(hx, q.ix, q.nox);
+    const float t0y = fmaf(ly, q.iy, q.noy), t1y = fmaf(hy, q.iy, q.noy);
+    const float t0z = fmaf(lz, q.iz, q.noz), t1z = fmaf(hz, q.iz, q.noz);
+    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), lo));
+    const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), hi));
     *t_enter = tn;
     return tn <= tf;
 }
 
 // Entry and exit distance of a ray in a box, clamped to [lo, hi]; the box is
 // crossed inside the window when *tn <= *tf.  Same arithmetic as box_hit.
-__device__ __forceinline__ void box_span(float lx, float ly, float lz, float hx, float hy, float hz, float ox,
-                                         float oy, float oz, float ix, float iy, float iz, float lo, float hi,
-                                         float* tn, float* tf)
+__device__ __forceinline__ void box_span(float lx, float ly, float lz, float hx, float hy, float hz,
+                                         const SlabRay& q, float lo, float hi, float* tn, float* tf)
 {
-    float t0x = (lx - ox) * ix, t1x = (hx - ox) * ix;
-    float t0y = (ly - oy) * iy, t1y = (hy - oy) * iy;
-    float t0z = (lz - oz) * iz, t1z = (hz - oz) * iz;
+    const float t0x = fmaf(lx, q.ix, q.nox), t1x = fmaf(hx, q.ix, q.nox);
+    const float t0y = fmaf(ly, q.iy, q.noy), t1y = fmaf(hy, q.iy, q.noy);
+    const float t0z = fmaf(lz, q.iz, q.noz), t1z = fmaf(hz, q.iz, q.noz);
     *tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), lo));
     *tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), hi));
 }
@@ -202,6 +209,14 @@ __device__ __forceinline__ float safe_inv(float d)
     const float tiny = 1e-20f;
     float dd = fabsf(d) < tiny ? copysignf(tiny, d) : d;
     return 1.0f / dd;
+}
+
+__device__ __forceinline__ SlabRay slab_ray(const Ray& r)
+{
+    SlabRay q;
+    q.ix = safe_inv(r.dx), q.iy = safe_inv(r.dy), q.iz = safe_inv(r.dz);
+    q.nox = -(r.ox * q.ix), q.noy = -(r.oy * q.iy), q.noz = -(r.oz * q.iz);
+    return q;
 }
 
 }  // namespace irgs

@@ -115,8 +115,8 @@ __device__ __forceinline__ glb_int* as_glb(int* p) { return (glb_int*)p; }
 // cluster leaves are tested on the spot, inner children are visited nearest
 // first (the others are pushed farthest first).
 template <int K>
-__device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, const Ray& ray, float ix, float iy,
-                                            float iz, float t_min, float t_max, uint64_t after, Stack& st,
+__device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, const Ray& ray, const SlabRay& q,
+                                            float t_min, float t_max, uint64_t after, Stack& st,
                                             Counters& ct)
 {
     ++ct.rounds;
@@ -133,10 +133,10 @@ __device__ __forceinline__ void collect_bvh(KBuf<K>& kb, const SceneView& sc, co
         const float hi = kb.full() ? fminf(key_tau(kb.last()), tmax_c) : tmax_c;
         float te[4];
         bool h[4];
-        h[0] = box_hit(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[0]);
-        h[1] = box_hit(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[1]);
-        h[2] = box_hit(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[2]);
-        h[3] = box_hit(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, hi, &te[3]);
+        h[0] = box_hit(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, q, lo, hi, &te[0]);
+        h[1] = box_hit(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, q, lo, hi, &te[1]);
+        h[2] = box_hit(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, q, lo, hi, &te[2]);
+        h[3] = box_hit(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, q, lo, hi, &te[3]);
         const int c4[4] = {ch.x, ch.y, ch.z, ch.w};
         float key[4];
         int ref[4];

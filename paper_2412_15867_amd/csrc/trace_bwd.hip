@@ -254,7 +254,7 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
 {
     float S = 0.0f;
     Counters ct;
-    const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
+    const SlabRay q = slab_ray(ray);
     uint64_t after = 0;
     float T = 1.0f;
     int nh = 0;
@@ -266,7 +266,7 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
                                                  __uint_as_float(static_cast<uint32_t>(after)), T, __int_as_float(nh));
         KBuf<K> kb;
         kb.clear();
-        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
+        collect_bvh<K>(kb, sc, ray, q, P.t_min, P.t_max, after, st, ct);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < kb.cnt && !done) {
@@ -291,14 +291,14 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
         KBuf<K> kb;
         for (int adv = base; adv < rr; ++adv) {  // rounds past the last checkpoint
             kb.clear();
-            collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
+            collect_bvh<K>(kb, sc, ray, q, P.t_min, P.t_max, after, st, ct);
 #pragma unroll
             for (int j = 0; j < K; ++j) T = j < kb.cnt ? T * (1.0f - entry_alpha(sc, ray, kb.pos(j))) : T;
             nb += kb.cnt;
             after = kb.last();
         }
         kb.clear();
-        collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
+        collect_bvh<K>(kb, sc, ray, q, P.t_min, P.t_max, after, st, ct);
         const int m = min(kb.cnt, total - nb);
         float Tj[K];
 #pragma unroll

@@ -155,17 +155,18 @@ template <int K, int FM, class Source>
 __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long* next_ray, const TraceParams& P,
                                            Stack& st, Deferred dq)
 {
-    enum { kTrav = 0, kComp = 1, kFetch = 2, kDead = 3 };
+    enum { kTrav = 0, kComp = 1, kFetch = 2, kDead = 3, kIns = 4 };
     const float inf = __int_as_float(0x7f800000);
     LaneRay lr;
     Ray ray;
-    float ix = 0.0f, iy = 0.0f, iz = 0.0f;
+    SlabRay q{};
     float T = 1.0f, O = 0.0f, D = 0.0f;
     float acc[FM];
 #pragma unroll
     for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
     int nh = 0;
-    uint64_t after = 0, round_last = 0;
+    uint64_t after = 0;          // resume key; while compositing, the key just composited
+    uint64_t pend = kKeyNone;    // hit key waiting for the insert step (mode kIns)
     bool round_full = false, term = false;
     int cur = kItemEmpty;
     int mode = kFetch;
@@ -182,11 +183,13 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         // most lanes are waiting for (wave-uniform branch); the rest wait.
         const bool want_node = mode == kTrav && cur != kItemEmpty && cur >= 0;
         const bool want_leaf = mode == kTrav && cur < 0;
-        const bool want_other = mode != kDead && !want_node && !want_leaf;
-        const uint64_t bn = __ballot(want_node), bl = __ballot(want_leaf), bo = __ballot(want_other);
-        if ((bn | bl | bo) == 0) break;
-        const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
-        if (cn >= cl && cn >= co) {
+        const bool want_ins = mode == kIns;
+        const bool want_other = mode != kDead && !want_ins && !want_node && !want_leaf;
+        const uint64_t bn = __ballot(want_node), bl = __ballot(want_leaf), bi = __ballot(want_ins),
+                       bo = __ballot(want_other);
+        if ((bn | bl | bi | bo) == 0) break;
+        const int cn = __popcll(bn), cl = __popcll(bl), ci = __popcll(bi), co = __popcll(bo);
+        if (cn >= cl && cn >= ci && cn >= co) {
             if (want_node) {
                 ++ct.nodes;
                 const float4* np = reinterpret_cast<const float4*>(src.view(lr).wnodes + cur);
@@ -197,14 +200,10 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const float hi = kb.full() ? fminf(key_tau(kb.last()), tmax_c) : tmax_c;
                 float key[4], tn[4], tf[4];
                 int ref[4] = {ch.x, ch.y, ch.z, ch.w};
-                box_span(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[0],
-                         &tf[0]);
-                box_span(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[1],
-                         &tf[1]);
-                box_span(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[2],
-                         &tf[2]);
-                box_span(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ray.ox, ray.oy, ray.oz, ix, iy, iz, lo, tmax_c, &tn[3],
-                         &tf[3]);
+                box_span(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, q, lo, tmax_c, &tn[0], &tf[0]);
+                box_span(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, q, lo, tmax_c, &tn[1], &tf[1]);
+                box_span(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, q, lo, tmax_c, &tn[2], &tf[2]);
+                box_span(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, q, lo, tmax_c, &tn[3], &tf[3]);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     // an empty slot has an all +inf box, which is never crossed
@@ -233,26 +232,35 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 if (key[1] < inf) st.push(ref[1]);
                 cur = key[0] < inf ? ref[0] : next_item();
             }
-        } else if (cl >= co) {
-            // Test one surfel; the buffer insert runs outside the divergent
-            // region (predicated), so the buffer needs no per-branch copy.
-            bool ins = false;
-            uint64_t key = kKeyNone;
+        } else if (cl >= ci && cl >= co) {
+            // Test one surfel.  A hit for the buffer waits in `pend` for an
+            // insert step, which the wave runs once enough lanes hold one.
             if (want_leaf) {
                 const int first = (cur & ~kLeafBit) >> 4;
                 const int cnt = (cur & 15) + 1;
                 ++ct.tests;
                 float tau, rho2;
                 const bool hit = hit_test(load_rec(src.view(lr).rec, first), ray, P.t_min, P.t_max, &tau, &rho2);
-                key = hit_key(tau, first);
+                const uint64_t key = hit_key(tau, first);
                 const bool above = hit && key > after;
-                ins = above && key < kb.last();
+                const bool ins = above && key < kb.last();
                 if (above && !ins) dq.put(cluster_ref(first, 1));  // beyond this round's K-th key
                 cur = cnt > 1 ? cluster_ref(first + 1, cnt - 1) : next_item();
+                if (ins) {
+                    pend = key;
+                    mode = kIns;
+                }
             }
-            ct.inserts += ins ? 1 : 0;
-            const uint64_t ev = kb.insert_if(ins, key);
-            if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
+        } else if (ci >= co) {
+            // Insert step, predicated over the wave (the buffer is modified
+            // outside any divergent region, so it needs no per-branch copy).
+            const uint64_t ev = kb.insert_if(want_ins, pend);
+            if (want_ins) {
+                ++ct.inserts;
+                if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
+                pend = kKeyNone;
+                mode = kTrav;
+            }
         } else if (want_other) {
             if (mode == kFetch) {
                 if (!src.load(claim_slot(next_ray), lr, ray)) {
@@ -269,7 +277,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     if (src.view(lr).n <= 0 || !ray_valid(ray)) {
                         write_result<FM>(src, lr, O, D, T, acc, nh, ct);
                     } else {
-                        ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
+                        q = slab_ray(ray);
                         cur = 0;
                         st.sp = 0;
                         ++ct.rounds;
@@ -278,10 +286,10 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 }
             } else if (mode == kTrav) {  // stack and deferred input drained: the buffer is final
                 round_full = kb.full();
-                round_last = kb.last();
                 mode = kComp;
             } else if (kb.cnt > 0 && !term) {
                 const int pos = kb.pos(0);
+                after = kb.k[0];
 #pragma unroll
                 for (int j = 0; j < K - 1; ++j) kb.k[j] = kb.k[j + 1];
                 kb.k[K - 1] = kKeyNone;
@@ -310,8 +318,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 write_result<FM>(src, lr, O, D, T, acc, nh, ct);
                 mode = kFetch;
             } else {
-                after = round_last;
-                kb.clear();
+                kb.clear();  // `after` is the round's last (K-th) key
                 st.sp = 0;
                 ++ct.rounds;
                 cur = dq.flip() ? next_item() : 0;  // deferred list, or the root after an overflow

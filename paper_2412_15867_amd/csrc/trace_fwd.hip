@@ -37,14 +37,14 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
     int nh = 0;
     Counters ct;
     if (sc.n > 0 && ray_valid(ray)) {
-        const float ix = safe_inv(ray.dx), iy = safe_inv(ray.dy), iz = safe_inv(ray.dz);
+        const SlabRay q = slab_ray(ray);
         uint64_t after = 0;  // resume key: hits strictly above it (0 = from the start)
         bool done = false;
         while (!done) {
             KBuf<K> kb;
             kb.clear();
             if (BVH)
-                collect_bvh<K>(kb, sc, ray, ix, iy, iz, P.t_min, P.t_max, after, st, ct);
+                collect_bvh<K>(kb, sc, ray, q, P.t_min, P.t_max, after, st, ct);
             else
                 collect_all<K>(kb, sc, ray, P.t_min, P.t_max, after, ct);
 #pragma unroll
