@@ -23,7 +23,7 @@ def c1():
 
 def run(scene_np, ro, rd, hit_cap=256, **kw):
     from paper_2412_15867_amd import trace
-    scene = make_scene(scene_np, **{k: kw.pop(k) for k in ("alpha_min", "support_sigma") if k in kw})
+    scene = make_scene(scene_np, **{k: kw.pop(k) for k in ("alpha_min", "support_sigma", "leaf_size") if k in kw})
     res = trace(scene, dev(ro), dev(rd), hit_cap=hit_cap, **kw)
     torch.cuda.synchronize()
     out = to_np(res)
@@ -50,6 +50,20 @@ def test_c1_brute_force_equals_bvh_bitwise(c1):
     b = run(sc, ro, rd, k=16)
     for key in ("O", "F", "D", "T", "n_hits"):
         assert np.array_equal(a[key], b[key]), key
+    m = np.arange(256)[None, :] < a["n_hits"][:, None]
+    assert np.array_equal(np.where(m, a["hit_ids"], -1), np.where(m, b["hit_ids"], -1))
+
+
+@pytest.mark.parametrize("leaf", [1, 3, 16])
+def test_leaf_size_does_not_change_the_result(c1, leaf):
+    """Cluster leaves change only which boxes are tested: every leaf size
+    gives the brute-force tracer's output bit for bit."""
+    sc, ro, rd = c1
+    note(f"c1 leaf={leaf}")
+    a = run(sc, ro, rd, k=16, brute_force=True)
+    b = run(sc, ro, rd, k=16, leaf_size=leaf)
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(a[key], b[key]), (leaf, key)
     m = np.arange(256)[None, :] < a["n_hits"][:, None]
     assert np.array_equal(np.where(m, a["hit_ids"], -1), np.where(m, b["hit_ids"], -1))
 
