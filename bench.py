@@ -34,10 +34,59 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "k_trace_traffic_1M_surfels_4M_rays.md")
+CSRC = os.path.join(ROOT, "paper_2412_15867_amd", "csrc")
+FWD_SOURCES = ("trace_fwd.hip", "trace_flat.hpp", "march.hpp", "irgs_device.hpp", "irgs_internal.hpp")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def forward_fingerprint() -> str:
+    """Hash of the forward kernel's sources: measured traffic is reported
+    only while the kernel is the one the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in FWD_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM-side bytes of one in-step forward launch from the committed
+    rocprofv3 summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the
+    same counter reads for a device copy of known size), or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            for ln in fh:
+                if ln.startswith("traffic-data: "):
+                    d = json.loads(ln[len("traffic-data: "):])
+                    break
+            else:
+                return None
+    except OSError:
+        return None
+    if d.get("kernel_fingerprint") != forward_fingerprint():
+        return None
+    rd_scale = d["copy_bytes"] / (d["copy_fetch_kib"] * 1024.0)
+    wr_scale = d["copy_bytes"] / (d["copy_write_kib"] * 1024.0)
+    return round(d["fetch_kib"] * 1024.0 * rd_scale + d["write_kib"] * 1024.0 * wr_scale)
+
+
+def calibration_copy(nbytes: int = 512 << 20, reps: int = 3):
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {reps} x {nbytes} bytes")
 
 
 def fwd_bytes(n_hits: np.ndarray, F: int) -> float:
@@ -199,7 +248,8 @@ def run_c3(args):
         "bvh_depth": info["max_depth"],
         "roofline": {"bound": "hbm", "kernel": "k_trace (forward)" if dom_is_fwd else "k_backward",
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": measured_traffic() if dom_is_fwd else None,
                      "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": round(dom_ms, 3)},
         "roofline_fwd": {"achieved": round(fb / (fwd_only_ms * 1e-3) / 1e9, 3), "bytes": fb},
     }
@@ -428,6 +478,8 @@ def main():
     ap.add_argument("--recompute", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a 512 MiB device copy (for scaling profiled FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the trace shards rays across GPUs with no exchange in the "
@@ -442,6 +494,8 @@ def main():
         line = run_serve(args)
     else:
         line = run_c5(args)
+    if args.calibrate_copy:
+        calibration_copy()
     print(json.dumps(line), flush=True)
 
 

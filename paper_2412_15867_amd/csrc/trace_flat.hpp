@@ -233,19 +233,35 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 cur = key[0] < inf ? ref[0] : next_item();
             }
         } else if (cl >= ci && cl >= co) {
-            // Test one surfel.  A hit for the buffer waits in `pend` for an
-            // insert step, which the wave runs once enough lanes hold one.
+            // Test the next surfels of the current cluster: both records of
+            // a pair are fetched together (one memory round trip), the
+            // second is tested only if the first does not enter the buffer.
+            // A hit for the buffer waits in `pend` for an insert step, which
+            // the wave runs once enough lanes hold one.
             if (want_leaf) {
                 const int first = (cur & ~kLeafBit) >> 4;
                 const int cnt = (cur & 15) + 1;
+                const SurfelRec* recs = src.view(lr).rec;
+                const SurfelRec s0 = load_rec(recs, first);
+                const SurfelRec s1 = load_rec(recs, cnt > 1 ? first + 1 : first);
+                int used = 1;
                 ++ct.tests;
                 float tau, rho2;
-                const bool hit = hit_test(load_rec(src.view(lr).rec, first), ray, P.t_min, P.t_max, &tau, &rho2);
-                const uint64_t key = hit_key(tau, first);
-                const bool above = hit && key > after;
-                const bool ins = above && key < kb.last();
+                bool hit = hit_test(s0, ray, P.t_min, P.t_max, &tau, &rho2);
+                uint64_t key = hit_key(tau, first);
+                bool above = hit && key > after;
+                bool ins = above && key < kb.last();
                 if (above && !ins) dq.put(cluster_ref(first, 1));  // beyond this round's K-th key
-                cur = cnt > 1 ? cluster_ref(first + 1, cnt - 1) : next_item();
+                if (!ins && cnt > 1) {
+                    used = 2;
+                    ++ct.tests;
+                    hit = hit_test(s1, ray, P.t_min, P.t_max, &tau, &rho2);
+                    key = hit_key(tau, first + 1);
+                    above = hit && key > after;
+                    ins = above && key < kb.last();
+                    if (above && !ins) dq.put(cluster_ref(first + 1, 1));
+                }
+                cur = cnt > used ? cluster_ref(first + used, cnt - used) : next_item();
                 if (ins) {
                     pend = key;
                     mode = kIns;
