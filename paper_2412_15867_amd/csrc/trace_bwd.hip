@@ -33,6 +33,7 @@ constexpr int kHashFill = kHashSlots * 3 / 4;  // no new keys once this many slo
 constexpr int kNearHits = 24;    // only a ray's first hits (shared by neighbouring rays) use the table
 constexpr int kLdsFeat = 8;      // feature gradients pre-reduced in LDS (the rest go straight to global)
 constexpr int kLdsComp = 10 + kLdsFeat;
+constexpr int kValRow = kHashSlots + 1;  // value rows padded by a word: a row per component, lanes reading one slot hit different banks
 
 // Per-surfel gradient components of one hit: mu (3), raw quaternion (4),
 // scales (2), opacity (1), features (F).
@@ -48,7 +49,7 @@ struct HitGrad {
 // global atomics.
 struct GradAcc {
     int* keys;     // kHashSlots, -1 = empty
-    float* vals;   // [kLdsComp][kHashSlots]
+    float* vals;   // [kLdsComp][kValRow]
     int* filled;   // slots taken in this chunk
     float* gbuf;   // per-surfel interleaved accumulator: gbuf[id * gs + c]
     int gs;        // stride of gbuf in floats (a multiple of 32: one 128 B line per surfel at F <= 22)
@@ -94,7 +95,7 @@ struct GradAcc {
         if (found < 0) return false;
 #pragma unroll
         for (int c = 0; c < kLdsComp && c < 10 + FM; ++c) {
-            if (c < 10 + F) atomicAdd(vals + c * kHashSlots + found, h.g[c]);
+            if (c < 10 + F) atomicAdd(vals + c * kValRow + found, h.g[c]);
             h.g[c] = 0.0f;
         }
         return true;
@@ -109,7 +110,7 @@ struct GradAcc {
             const int slot = flat / nc, c = flat - slot * nc;
             const int id = keys[slot];
             if (id < 0) continue;
-            const float v = vals[c * kHashSlots + slot];
+            const float v = vals[c * kValRow + slot];
             if (v != 0.0f) atomicAdd(gbuf + static_cast<int64_t>(id) * gs + c, v);
         }
     }
@@ -118,7 +119,7 @@ struct GradAcc {
     {
         if (tid == 0) *filled = 0;
         for (int i = tid; i < kHashSlots; i += kBwdBlock) keys[i] = -1;
-        for (int i = tid; i < kLdsComp * kHashSlots; i += kBwdBlock) vals[i] = 0.0f;
+        for (int i = tid; i < kLdsComp * kValRow; i += kBwdBlock) vals[i] = 0.0f;
     }
 };
 
@@ -326,11 +327,15 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
                                                         unsigned long long* next_chunk)
 {
     __shared__ int hkeys[kHashSlots];
-    __shared__ float hvals[kLdsComp * kHashSlots];
+    __shared__ float hvals[kLdsComp * kValRow];
     __shared__ int hfilled;
     __shared__ long long claimed;
     __shared__ int stage_id[kBwdBlock];
-    __shared__ float stage[(10 + FM) * kBwdBlock];
+    // staged gradients, one row per component; rows padded by one word so
+    // that the scatter's reads (consecutive lanes: consecutive components
+    // of one hit) fall in different banks
+    constexpr int kRow = kBwdBlock + 1;
+    __shared__ float stage[(10 + FM) * kRow];
     const int tid = threadIdx.x;
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBwdBlock + tid;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBwdBlock;
@@ -389,7 +394,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
             }
             stage_id[tid] = id;
 #pragma unroll
-            for (int k = 0; k < 10 + FM; ++k) stage[k * kBwdBlock + tid] = hg.g[k];
+            for (int k = 0; k < 10 + FM; ++k) stage[k * kRow + tid] = hg.g[k];
             __syncthreads();
             // Transposed scatter: lane l takes component (q*64 + l) % nc of
             // hit (q*64 + l) / nc, so consecutive lanes add consecutive
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
             for (int flat = tid; flat < kBwdBlock * nc; flat += kBwdBlock) {
                 const int hit = flat / nc, comp = flat - hit * nc;
                 const int sid = stage_id[hit];
-                const float v = stage[comp * kBwdBlock + hit];
+                const float v = stage[comp * kRow + hit];
                 if (sid >= 0 && v != 0.0f) atomicAdd(gbuf + static_cast<int64_t>(sid) * gs + comp, v);
             }
             __syncthreads();
