@@ -89,7 +89,7 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
 }
 
 template <int K, int FM, bool BVH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : 1))) void k_trace(SceneView sc, TraceParams P, int64_t R,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 && FM <= 8 ? 4 : 1))) void k_trace(SceneView sc, TraceParams P, int64_t R,
                                                   const float* __restrict__ ro, const float* __restrict__ rd,
                                                   OutPtrs out, FlatScratch fs)
 {
