@@ -210,6 +210,26 @@ def surface200k():
     return sc, ro, rd
 
 
+def test_uncapped_proxy_radius(c1):
+    """The paper's own proxy (Eq. 5): support radius sqrt(2 ln(o / alpha_min))
+    with no 3-sigma cap (support_sigma = inf), against the oracle run with
+    the same reading; more hits than with the cap, never fewer."""
+    sc, ro, rd = c1
+    note("c1 uncapped proxy radius")
+    g = run(sc, ro, rd, k=16, support_sigma=float("inf"))
+    st = validate(sc.astuple(), ro, rd, g, sigma=float("inf"))
+    assert st["exact_eligible"] > 0.9 * st["rays"]
+    capped = run(sc, ro, rd, k=16, hit_cap=0)
+    # rays that did not stop at the cutoff without the cap composited all their
+    # hits, a superset of the capped hits (which then did not stop either)
+    full = g["T"] >= 1e-4
+    assert np.all(g["n_hits"][full] >= capped["n_hits"][full])
+    assert g["n_hits"].sum() > capped["n_hits"].sum()
+    b = run(sc, ro, rd, k=16, support_sigma=float("inf"), brute_force=True)
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(b[key], g[key]), key
+
+
 def test_surface_200k_full_launch_sampled(surface200k):
     """200K surfels, all 4.2M Monte Carlo rays traced in one launch; a seeded
     sample of 768 rays is validated against the brute-force oracle."""

@@ -66,7 +66,10 @@ def validate(surfels, ro, rd, gpu, rays=None, T_min=1e-4, alpha_min=1.0 / 255.0,
         eps_tau = 4e-6 * (1.0 + w) / np.maximum(cosn, 1e-12)          # FP32 depth error bound
         eps_u = 2.0 * eps_tau / np.minimum(sc[ids, 0], sc[ids, 1])     # in units of the scale
         rho = np.sqrt(rho2)
-        amb = ((np.abs(rho2 - sigma * sigma) <= np.maximum(1e-3, 2 * sigma * eps_u)) |
+        # with an infinite support radius (Eq. 5's proxy alone) only alpha_min decides the support
+        sup_amb = (np.abs(rho2 - sigma * sigma) <= np.maximum(1e-3, 2 * sigma * eps_u)) if np.isfinite(sigma) \
+            else np.zeros(cnt, bool)
+        amb = (sup_amb |
                (np.abs(alpha - alpha_min) <= alpha_min * np.maximum(1e-3, rho * eps_u)) |
                (np.abs(tau - t_min) <= np.maximum(1e-6, eps_tau)) |
                (np.abs(tau - t_max) <= np.maximum(1e-6, eps_tau)))
