@@ -11,6 +11,11 @@ code with the HIP library and never calls it.
                      (t_min, t_max), with its FP64 depth, u^2+v^2 and alpha.
 * ``replay``      -- FP64 compositing of a given ordered hit list.
 * ``frames``      -- tangent frame (t_u, t_v, n) of each quaternion.
+* ``sh_basis``    -- real spherical-harmonic basis of directions (degree <= 3),
+                     by the associated-Legendre recurrence; with ``sh_deg`` >= 0
+                     ``trace`` / ``replay`` read the features as RGB SH
+                     coefficients and composite the view-dependent colour
+                     max(Y(d).k + 1/2, 0) (3 output channels).
 * ``grad``        -- (submodule) FP64 autograd gradients over a given hit list
                      and central finite differences.
 
@@ -28,12 +33,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trace_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-DEFAULTS = dict(alpha_min=1.0 / 255.0, T_min=1e-4, t_min=0.0, t_max=float("inf"), sigma=3.0)
+DEFAULTS = dict(alpha_min=1.0 / 255.0, T_min=1e-4, t_min=0.0, t_max=float("inf"), sigma=3.0, sh_deg=-1)
 
 
 class Params(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_double), ("T_min", ctypes.c_double),
-                ("t_min", ctypes.c_double), ("t_max", ctypes.c_double), ("sigma", ctypes.c_double)]
+                ("t_min", ctypes.c_double), ("t_max", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("sh_deg", ctypes.c_int32)]
 
 
 def build(force: bool = True) -> str:
@@ -63,8 +69,10 @@ def lib():
                                      P, P, P, P, P, P, i32]
         L.orc_candidates.restype = ctypes.c_int
         L.orc_replay.argtypes = [i64, i32, P, P, P, P, P, i64, P, P, i32, P, P,
-                                 P, P, P, P, P, P, P, i32]
+                                 P, P, P, P, P, P, P, i32, i32]
         L.orc_replay.restype = ctypes.c_int
+        L.orc_sh_basis.argtypes = [i64, P, i32, P]
+        L.orc_sh_basis.restype = None
         L.orc_surfel_frames.argtypes = [i64, P, P, P, P]
         L.orc_surfel_frames.restype = None
         L.orc_max_threads.argtypes = []
@@ -84,7 +92,16 @@ def _p(a: np.ndarray):
 def make_params(**kw) -> Params:
     d = dict(DEFAULTS)
     d.update({k: v for k, v in kw.items() if k in d})
-    return Params(d["alpha_min"], d["T_min"], d["t_min"], d["t_max"], d["sigma"])
+    return Params(d["alpha_min"], d["T_min"], d["t_min"], d["t_max"], d["sigma"], int(d["sh_deg"]))
+
+
+def out_channels(F: int, sh_deg: int) -> int:
+    """Composited feature channels: 3 colours in SH mode, else F."""
+    if sh_deg >= 0:
+        if F != 3 * (sh_deg + 1) ** 2:
+            raise ValueError(f"SH degree {sh_deg} needs {3 * (sh_deg + 1) ** 2} features, got {F}")
+        return 3
+    return F
 
 
 def _surfels(s):
@@ -104,10 +121,10 @@ def trace(surfels, ro, rd, hit_cap: int = 0, nthreads: int = 0, **kw):
     ro, rd = _d(ro).reshape(-1, 3), _d(rd).reshape(-1, 3)
     N, F, R = mu.shape[0], feat.shape[1], ro.shape[0]
     O, D, T = np.zeros(R), np.zeros(R), np.ones(R)
-    Fo = np.zeros((R, F))
+    prm = make_params(**kw)
+    Fo = np.zeros((R, out_channels(F, prm.sh_deg)))
     nh = np.zeros(R, dtype=np.int32)
     hits = np.full((R, max(hit_cap, 1)), -1, dtype=np.int32)
-    prm = make_params(**kw)
     rc = lib().orc_trace(N, F, _p(mu), _p(quat), _p(scale), _p(opac), _p(feat), R, _p(ro), _p(rd),
                          ctypes.byref(prm), _p(O), _p(Fo), _p(D), _p(T), _p(nh), hit_cap,
                          _p(hits) if hit_cap > 0 else None, nthreads)
@@ -137,7 +154,7 @@ def candidates(surfels, ro, rd, cap: int = 512, band: float = 1e-2, nthreads: in
     return dict(ids=ids, tau=tau, rho2=rho2, alpha=alpha, hit=hit.astype(bool), count=cnt)
 
 
-def replay(surfels, ro, rd, lists, lengths, nthreads: int = 0):
+def replay(surfels, ro, rd, lists, lengths, nthreads: int = 0, sh_deg: int = -1):
     """Composite the given ordered lists (R, H) int32 of length `lengths`."""
     mu, quat, scale, opac, feat = _surfels(surfels)
     ro, rd = _d(ro).reshape(-1, 3), _d(rd).reshape(-1, 3)
@@ -146,13 +163,13 @@ def replay(surfels, ro, rd, lists, lengths, nthreads: int = 0):
     N, F, R = mu.shape[0], feat.shape[1], ro.shape[0]
     H = lists.shape[1]
     O, D, T = np.zeros(R), np.zeros(R), np.ones(R)
-    Fo = np.zeros((R, F))
+    Fo = np.zeros((R, out_channels(F, sh_deg)))
     Tpost = np.ones((R, H))
     tau = np.zeros((R, H))
     alpha = np.zeros((R, H))
     lib().orc_replay(N, F, _p(mu), _p(quat), _p(scale), _p(opac), _p(feat), R, _p(ro), _p(rd), H,
                      _p(lists), _p(lengths), _p(O), _p(Fo), _p(D), _p(T), _p(Tpost), _p(tau), _p(alpha),
-                     nthreads)
+                     int(sh_deg), nthreads)
     return dict(O=O, F=Fo, D=D, T=T, Tpost=Tpost, tau=tau, alpha=alpha)
 
 
@@ -162,3 +179,11 @@ def frames(quat):
     tu, tv, n = np.zeros((N, 3)), np.zeros((N, 3)), np.zeros((N, 3))
     lib().orc_surfel_frames(N, _p(quat), _p(tu), _p(tv), _p(n))
     return tu, tv, n
+
+
+def sh_basis(dirs, deg: int) -> np.ndarray:
+    """Real SH basis Y[l*l + l + m] (R, (deg+1)^2) of the normalised directions."""
+    dirs = _d(dirs).reshape(-1, 3)
+    Y = np.zeros((dirs.shape[0], (deg + 1) ** 2))
+    lib().orc_sh_basis(dirs.shape[0], _p(dirs), int(deg), _p(Y))
+    return Y

@@ -14,6 +14,12 @@ with respect to the raw parameters (centre, raw quaternion, scales, opacity,
 features).  Selection and order of the hits are piecewise constant in the
 parameters, so they carry no gradient; the list is an input.
 
+With ``sh_deg`` >= 0 the features are RGB coefficients of the real SH basis
+and each hit contributes the colour max(Y(d).k + 1/2, 0) along the ray's
+normalised direction d (3 output channels).  The basis here comes from
+``scipy.special.sph_harm_y`` (an implementation independent of the C
+oracle's recurrence).
+
 ``fd_grad`` takes central finite differences of the same L through the
 brute-force C oracle (which re-selects and re-sorts the hits at each
 perturbed point) and skips every parameter whose perturbation changes any
@@ -40,7 +46,23 @@ def _frame(q):
     return tu, tv, n
 
 
-def composite_given_hits(mu, quat, scale, opac, feat, ro, rd, lists):
+def sh_basis_scipy(rd, deg: int) -> np.ndarray:
+    """Real SH basis Y[l*l + l + m] of the ray directions: sqrt(2) Re / sqrt(2)
+    Im of scipy's complex harmonics (Condon-Shortley phase) for m > 0 / m < 0."""
+    from scipy.special import sph_harm_y
+    d = np.asarray(rd, np.float64).reshape(-1, 3)
+    d = d / np.linalg.norm(d, axis=1, keepdims=True)
+    polar = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+    azim = np.arctan2(d[:, 1], d[:, 0])
+    Y = np.zeros((d.shape[0], (deg + 1) ** 2))
+    for l in range(deg + 1):
+        for m in range(-l, l + 1):
+            c = sph_harm_y(l, abs(m), polar, azim)
+            Y[:, l * l + l + m] = c.real if m == 0 else np.sqrt(2.0) * (c.real if m > 0 else c.imag)
+    return Y
+
+
+def composite_given_hits(mu, quat, scale, opac, feat, ro, rd, lists, sh_deg: int = -1):
     """O, F, D, T of each ray from its ordered list (R, H) (-1 = padding)."""
     valid = lists >= 0
     idx = lists.clamp(min=0)
@@ -65,20 +87,25 @@ def composite_given_hits(mu, quat, scale, opac, feat, ro, rd, lists):
     T = torch.cumprod(torch.cat([one, 1.0 - alpha[:, :-1]], 1), 1)   # Eq. 2
     w = T * alpha
     O = w.sum(1)
+    if sh_deg >= 0:
+        nb = (sh_deg + 1) ** 2
+        Y = torch.tensor(sh_basis_scipy(rd.detach().numpy(), sh_deg))          # (R, nb), no gradient
+        k = f.reshape(f.shape[0], f.shape[1], nb, 3)
+        f = torch.relu((Y[:, None, :, None] * k).sum(2) + 0.5)                 # view-dependent colour
     F = (w[..., None] * f).sum(1)
     D = (w * tau).sum(1)
     Tend = T[:, -1] * (1.0 - alpha[:, -1]) if alpha.shape[1] else torch.ones_like(O)
     return O, F, D, Tend
 
 
-def grad_given_hits(surfels, ro, rd, lists, gO, gF, gD):
+def grad_given_hits(surfels, ro, rd, lists, gO, gF, gD, sh_deg: int = -1):
     """Gradients (dict of float64 numpy arrays) of L over given hit lists."""
     ts = [torch.tensor(np.asarray(a, dtype=np.float64), requires_grad=True) for a in surfels]
     feat = ts[4].reshape(ts[0].shape[0], -1)
     ro_t = torch.tensor(np.asarray(ro, dtype=np.float64)).reshape(-1, 3)
     rd_t = torch.tensor(np.asarray(rd, dtype=np.float64)).reshape(-1, 3)
     L_t = torch.tensor(np.asarray(lists, dtype=np.int64))
-    O, F, D, _ = composite_given_hits(ts[0], ts[1], ts[2], ts[3].reshape(-1), feat, ro_t, rd_t, L_t)
+    O, F, D, _ = composite_given_hits(ts[0], ts[1], ts[2], ts[3].reshape(-1), feat, ro_t, rd_t, L_t, sh_deg)
     gO_t = torch.tensor(np.asarray(gO, dtype=np.float64)).reshape(-1)
     gF_t = torch.tensor(np.asarray(gF, dtype=np.float64)).reshape(O.shape[0], -1)
     gD_t = torch.tensor(np.asarray(gD, dtype=np.float64)).reshape(-1)

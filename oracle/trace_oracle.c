@@ -31,6 +31,17 @@
  *     everything; a surfel with a non-finite parameter, a zero quaternion or
  *     a non-positive scale is never hit.
  *
+ * View-dependent colour (Sec. 3.1: each Gaussian's colour is modelled by
+ * spherical harmonics, and the trace uses that colour, Sec. 3.3): with
+ * sh_deg >= 0 the F features of a surfel are RGB coefficients of the real SH
+ * basis up to degree sh_deg, coefficient-major (F = 3 (sh_deg + 1)^2), and
+ * the colour a ray sees is, per channel, max(sum_j Y_j(d) k_j + 1/2, 0) with
+ * d the normalised ray direction.  Readings (the paper names SH only): the
+ * basis is sqrt(2) Re / sqrt(2) Im of the complex harmonics with the
+ * Condon-Shortley phase for m > 0 / m < 0, index j = l^2 + l + m; the 1/2
+ * offset and the clamp at 0 are those of the Gaussian-splatting colour
+ * model; the composited feature output then has 3 channels.
+ *
  * All inputs are FP64 (callers widen FP32 data exactly).  OpenMP over rays.
  */
 #include <math.h>
@@ -48,6 +59,7 @@ typedef struct {
     double t_min;
     double t_max;
     double sigma; /* support radius in units of the scales */
+    int32_t sh_deg; /* -1: plain features; 0..3: RGB SH coefficients */
 } orc_params;
 
 typedef struct {
@@ -61,6 +73,8 @@ typedef struct {
     double alpha;
     int32_t id;
 } orc_hit;
+
+static const double kPi = 3.14159265358979323846;
 
 static int finite3(const double* v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
 static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -106,6 +120,70 @@ void orc_surfel_frames(int64_t N, const double* quat, double* tu, double* tv, do
         double qn;
         quat_columns(quat + 4 * i, tu + 3 * i, tv + 3 * i, &qn);
         cross3(tu + 3 * i, tv + 3 * i, nrm + 3 * i);
+    }
+}
+
+/* Associated Legendre function P_l^m(x), 0 <= m <= l, with the
+ * Condon-Shortley phase, by the standard upward recurrence in l. */
+static double legendre(int l, int m, double x)
+{
+    double pmm = 1.0;
+    const double sx = sqrt(fmax(0.0, 1.0 - x * x));
+    for (int i = 1; i <= m; ++i) pmm *= -(2.0 * i - 1.0) * sx;
+    if (l == m) return pmm;
+    double p1 = x * (2.0 * m + 1.0) * pmm; /* P_{m+1}^m */
+    if (l == m + 1) return p1;
+    double p0 = pmm, pl = 0.0;
+    for (int ll = m + 2; ll <= l; ++ll) {
+        pl = ((2.0 * ll - 1.0) * x * p1 - (ll + m - 1.0) * p0) / (ll - m);
+        p0 = p1;
+        p1 = pl;
+    }
+    return pl;
+}
+
+static double factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+/* Real SH basis of the unit direction d (normalised here), degrees 0..deg:
+ * Y[l*l + l + m].  Polar angle from +z, azimuth from +x towards +y. */
+static void sh_basis(const double* d_in, int deg, double* Y)
+{
+    const double nrm = sqrt(dot3(d_in, d_in));
+    const double ct = d_in[2] / nrm;
+    const double phi = atan2(d_in[1], d_in[0]);
+    for (int l = 0; l <= deg; ++l) {
+        for (int m = 0; m <= l; ++m) {
+            const double N = sqrt((2.0 * l + 1.0) / (4.0 * kPi) * factorial(l - m) / factorial(l + m));
+            const double P = legendre(l, m, ct);
+            if (m == 0) {
+                Y[l * l + l] = N * P;
+            } else {
+                Y[l * l + l + m] = sqrt(2.0) * N * P * cos(m * phi);
+                Y[l * l + l - m] = sqrt(2.0) * N * P * sin(m * phi);
+            }
+        }
+    }
+}
+
+void orc_sh_basis(int64_t n, const double* dirs, int32_t deg, double* Y)
+{
+    const int nb = (deg + 1) * (deg + 1);
+    for (int64_t i = 0; i < n; ++i) sh_basis(dirs + 3 * i, deg, Y + i * nb);
+}
+
+/* Colour of one surfel seen along the ray whose basis is Y (3 channels). */
+static void sh_colour(const double* k, int deg, const double* Y, double* col)
+{
+    const int nb = (deg + 1) * (deg + 1);
+    for (int c = 0; c < 3; ++c) {
+        double v = 0.5;
+        for (int j = 0; j < nb; ++j) v += Y[j] * k[3 * j + c];
+        col[c] = v > 0.0 ? v : 0.0;
     }
 }
 
@@ -195,8 +273,11 @@ int orc_trace(int64_t N, int32_t F, const double* mu, const double* quat, const 
             const double* o_r = ro + 3 * r;
             const double* d_r = rd + 3 * r;
             double acc_O = 0.0, acc_D = 0.0, trans = 1.0;
-            double* acc_F = Fo + (size_t)r * F;
-            for (int c = 0; c < F; ++c) acc_F[c] = 0.0;
+            const int FO = P->sh_deg >= 0 ? 3 : F;
+            double* acc_F = Fo + (size_t)r * FO;
+            for (int c = 0; c < FO; ++c) acc_F[c] = 0.0;
+            double Y[16];
+            if (P->sh_deg >= 0 && ray_ok(o_r, d_r)) sh_basis(d_r, P->sh_deg, Y);
             int32_t* my_hits = hits ? hits + (size_t)r * hit_cap : NULL;
             if (my_hits)
                 for (int32_t h = 0; h < hit_cap; ++h) my_hits[h] = -1;
@@ -228,7 +309,13 @@ int orc_trace(int64_t N, int32_t F, const double* mu, const double* quat, const 
                 double w = trans * buf[h].alpha;
                 acc_O += w;
                 const double* f = feat + (size_t)buf[h].id * F;
-                for (int c = 0; c < F; ++c) acc_F[c] += w * f[c];
+                if (P->sh_deg >= 0) {
+                    double col[3];
+                    sh_colour(f, P->sh_deg, Y, col);
+                    for (int c = 0; c < 3; ++c) acc_F[c] += w * col[c];
+                } else {
+                    for (int c = 0; c < F; ++c) acc_F[c] += w * f[c];
+                }
                 acc_D += w * buf[h].tau;
                 trans *= (1.0 - buf[h].alpha);
                 if (my_hits && count < hit_cap) my_hits[count] = buf[h].id;
@@ -296,19 +383,22 @@ int orc_candidates(int64_t N, const double* mu, const double* quat, const double
 int orc_replay(int64_t N, int32_t F, const double* mu, const double* quat, const double* scale,
                const double* opac, const double* feat, int64_t R, const double* ro, const double* rd,
                int32_t H, const int32_t* list, const int32_t* len, double* O, double* Fo, double* D, double* T,
-               double* Tpost, double* tau_out, double* alpha_out, int32_t nthreads)
+               double* Tpost, double* tau_out, double* alpha_out, int32_t sh_deg, int32_t nthreads)
 {
     orc_surfel* S = build_surfels(N, mu, quat, scale, opac);
     if (!S) return -1;
     set_threads(nthreads);
-    orc_params loose = {0.0, 0.0, -INFINITY, INFINITY, INFINITY};
+    orc_params loose = {0.0, 0.0, -INFINITY, INFINITY, INFINITY, sh_deg};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < R; ++r) {
         const double* o_r = ro + 3 * r;
         const double* d_r = rd + 3 * r;
         double acc_O = 0.0, acc_D = 0.0, trans = 1.0;
-        double* acc_F = Fo + (size_t)r * F;
-        for (int c = 0; c < F; ++c) acc_F[c] = 0.0;
+        const int FO = sh_deg >= 0 ? 3 : F;
+        double* acc_F = Fo + (size_t)r * FO;
+        for (int c = 0; c < FO; ++c) acc_F[c] = 0.0;
+        double Y[16];
+        if (sh_deg >= 0 && ray_ok(o_r, d_r)) sh_basis(d_r, sh_deg, Y);
         for (int32_t h = 0; h < len[r] && h < H; ++h) {
             int32_t id = list[(size_t)r * H + h];
             double t = NAN, p2, a = NAN;
@@ -317,7 +407,13 @@ int orc_replay(int64_t N, int32_t F, const double* mu, const double* quat, const
             double w = trans * a;
             acc_O += w;
             const double* f = feat + (size_t)id * F;
-            for (int c = 0; c < F; ++c) acc_F[c] += w * f[c];
+            if (sh_deg >= 0) {
+                double col[3];
+                sh_colour(f, sh_deg, Y, col);
+                for (int c = 0; c < 3; ++c) acc_F[c] += w * col[c];
+            } else {
+                for (int c = 0; c < F; ++c) acc_F[c] += w * f[c];
+            }
             acc_D += w * t;
             trans *= (1.0 - a);
             if (Tpost) Tpost[(size_t)r * H + h] = trans;
