@@ -89,6 +89,16 @@ typedef struct {
 
 #define IRGS_FLAG_BRUTE_FORCE 1u /* trace: test every surfel, no BVH */
 #define IRGS_FLAG_RECOMPUTE 2u   /* backward: re-march instead of reading saved hits */
+/* trace / backward: view-dependent colour (Sec. 3.1 models each surfel's
+ * colour with spherical harmonics; the trace uses that colour, Sec. 3.3).
+ * The F = 3 (deg + 1)^2 features of a surfel (deg <= 3: F = 3, 12, 27, 48)
+ * are RGB coefficients of the real SH basis, coefficient-major
+ * (feat[i][3 j + c], j = l^2 + l + m; Y_lm = sqrt(2) Re / sqrt(2) Im of the
+ * complex harmonics with the Condon-Shortley phase for m > 0 / m < 0); each
+ * hit contributes, per channel, max(sum_j Y_j(d) k_j + 1/2, 0) with d the
+ * normalised ray direction.  out->feat and grad_in->g_feat are then R x 3;
+ * grads->feat stays N x F.  k must be 16 or 32; not for irgs_trace_packed. */
+#define IRGS_FLAG_SH 4u
 
 /* Outputs of a trace, caller-allocated (R = number of rays):
  *   opacity (R)      accumulated opacity O = sum T_i alpha_i (o_rt of Eq. 8;

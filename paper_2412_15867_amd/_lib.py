@@ -21,6 +21,7 @@ IRGS_E_HIP = -3
 IRGS_E_STATE = -4
 FLAG_BRUTE_FORCE = 1
 FLAG_RECOMPUTE = 2
+FLAG_SH = 4          # features are RGB SH coefficients; 3 composited channels
 
 
 class Surfels(ctypes.Structure):

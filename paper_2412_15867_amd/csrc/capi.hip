@@ -97,6 +97,14 @@ void free_scene_buffers(irgs_scene s)
     s->built = false;
 }
 
+// SH degree whose RGB coefficients make F features, or -1.
+int sh_degree(int32_t F)
+{
+    for (int d = 0; d <= 3; ++d)
+        if (F == 3 * (d + 1) * (d + 1)) return d;
+    return -1;
+}
+
 irgs_status check_params(const irgs_params* p, int32_t F)
 {
     if (!p) return fail(IRGS_E_INVALID, "params is NULL");
@@ -107,6 +115,11 @@ irgs_status check_params(const irgs_params* p, int32_t F)
     if (!(p->alpha_min >= 0.0f) || !(p->T_min >= 0.0f) || std::isnan(p->t_min) || std::isnan(p->t_max) ||
         !(p->support_sigma > 0.0f))
         return fail(IRGS_E_INVALID, "alpha_min, T_min >= 0, support_sigma > 0 and finite-or-inf t window required");
+    if (p->flags & IRGS_FLAG_SH) {
+        if (sh_degree(F) < 0)
+            return fail(IRGS_E_INVALID, "IRGS_FLAG_SH needs 3 (deg + 1)^2 features, deg <= 3 (3, 12, 27, 48); F = %d", F);
+        if (k != 16 && k != 32) return fail(IRGS_E_INVALID, "IRGS_FLAG_SH supports k = 16 or 32");
+    }
     return IRGS_OK;
 }
 
@@ -209,6 +222,7 @@ TraceParams trace_params(const irgs_params* p, int32_t F)
     t.t_max = p->t_max;
     t.T_min = p->T_min;
     t.F = F;
+    t.sh_deg = (p->flags & IRGS_FLAG_SH) ? sh_degree(F) : -1;
     return t;
 }
 
@@ -413,6 +427,7 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
     if (!p) return fail(IRGS_E_INVALID, "params is NULL");
     if (n_items < 0 || (n_items > 0 && !items)) return fail(IRGS_E_INVALID, "bad items");
     if (p->k != 16 && p->k != 32) return fail(IRGS_E_INVALID, "packed launch supports k = 16 or 32");
+    if (p->flags & IRGS_FLAG_SH) return fail(IRGS_E_INVALID, "IRGS_FLAG_SH is not supported by the packed launch");
     int32_t Fmax = 0;
     int slots = 0;
     std::vector<SceneView> views(n_scenes);

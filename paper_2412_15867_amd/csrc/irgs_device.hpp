@@ -74,7 +74,8 @@ struct SceneView {
 
 struct TraceParams {
     float t_min, t_max, T_min;
-    int32_t F;
+    int32_t F;       // features per surfel
+    int32_t sh_deg;  // -1: features composited as they are; 0..3: RGB SH coefficients (3 output channels)
 };
 
 struct Ray {
@@ -202,6 +203,57 @@ __device__ __forceinline__ void box_span(float lx, float ly, float lz, float hx,
     const float t0z = fmaf(lz, q.iz, q.noz), t1z = fmaf(hz, q.iz, q.noz);
     *tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), lo));
     *tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), hi));
+}
+
+// View-dependent colour (Sec. 3.1: each surfel's colour is modelled by
+// spherical harmonics; the trace uses that colour).  `k` holds RGB
+// coefficients of the real SH basis up to degree `deg`, coefficient-major
+// (k[3 j + c], j = l^2 + l + m); the colour seen along direction (dx, dy, dz)
+// (normalised here) is max(sum_j Y_j k[3 j + c] + 1/2, 0) per channel.  The
+// basis is sqrt(2) Re / sqrt(2) Im of the complex harmonics with the
+// Condon-Shortley phase (m > 0 / m < 0), written out as polynomials in the
+// unit direction; the constants are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!)
+// times the polynomial's own factor.
+__device__ __forceinline__ void sh_basis(float dx, float dy, float dz, int deg, float* Y)
+{
+    const float inv = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    const float x = dx * inv, y = dy * inv, z = dz * inv;
+    Y[0] = 0.28209479177387814f;  // 1 / (2 sqrt(pi))
+    if (deg < 1) return;
+    const float c1 = 0.48860251190291992f;  // sqrt(3 / (4 pi))
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792f * (x * y);          // sqrt(15 / (4 pi))
+    Y[5] = -1.0925484305920792f * (y * z);
+    Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);  // sqrt(5 / (16 pi))
+    Y[7] = -1.0925484305920792f * (x * z);
+    Y[8] = 0.54627421529603959f * (xx - yy);       // sqrt(15 / (16 pi))
+    if (deg < 3) return;
+    Y[9] = -0.59004358992664352f * (y * (3.0f * xx - yy));   // sqrt(35 / (32 pi))
+    Y[10] = 2.8906114426405538f * (x * y * z);               // sqrt(105 / (4 pi))
+    Y[11] = -0.45704579946446577f * (y * (5.0f * zz - 1.0f)); // sqrt(21 / (32 pi))
+    Y[12] = 0.37317633259011540f * (z * (5.0f * zz - 3.0f));  // sqrt(7 / (16 pi))
+    Y[13] = -0.45704579946446577f * (x * (5.0f * zz - 1.0f));
+    Y[14] = 1.4453057213202769f * (z * (xx - yy));           // sqrt(105 / (16 pi))
+    Y[15] = -0.59004358992664352f * (x * (xx - 3.0f * yy));
+}
+
+// Raw colour sum_j Y_j k[3 j + c] + 1/2 (before the clamp at 0).
+__device__ __forceinline__ void sh_raw(const float* __restrict__ k, int deg, const float* Y, float* raw)
+{
+    const int nb = (deg + 1) * (deg + 1);
+    raw[0] = raw[1] = raw[2] = 0.5f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j < nb) {
+            raw[0] = fmaf(Y[j], k[3 * j], raw[0]);
+            raw[1] = fmaf(Y[j], k[3 * j + 1], raw[1]);
+            raw[2] = fmaf(Y[j], k[3 * j + 2], raw[2]);
+        }
+    }
 }
 
 __device__ __forceinline__ float safe_inv(float d)

@@ -129,10 +129,15 @@ struct GradAcc {
 // every surfel's gradient at FP32 accuracy.  Only the per-surfel
 // contributions are rounded to FP32 for accumulation.  The transmittance
 // before the hit (Ti) is the forward pass's own.
-template <int FM>
-__device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, const Ray& ray, float Ti_f, float& S_f,
-                                         float gO, const float* gF, float gD, HitGrad<FM>& h)
+// With SH the features are RGB coefficients: the hit's colour is recomputed
+// exactly as in the forward (FP32), and the coefficient gradients are
+// T alpha g_F,c Y_j(d) wherever the channel is not clamped.
+template <int FM, int FU, bool SH>
+__device__ __forceinline__ void grad_hit(const RawSurfels& raw, const TraceParams& P, int id, const Ray& ray,
+                                         float Ti_f, float& S_f, float gO, const float* gF, float gD,
+                                         HitGrad<FM>& h)
 {
+    const int F = P.F;
     const int64_t i = id;
     const double mx = raw.mu[3 * i], my = raw.mu[3 * i + 1], mz = raw.mu[3 * i + 2];
     const float4 qf = *reinterpret_cast<const float4*>(raw.quat + 4 * i);
@@ -159,17 +164,38 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, int F, int id, c
 
     double c = gO + gD * tau;
     const float* f = raw.feat + i * F;
-#pragma unroll
-    for (int k = 0; k < FM; ++k) {
-        const float fv = k < F ? f[k] : 0.0f;
-        c += double(gF[k]) * fv;
-    }
     const double wgt = Ti * alpha;
+    if constexpr (SH) {
+        float Y[16], col[3];
+        sh_basis(ray.dx, ray.dy, ray.dz, P.sh_deg, Y);
+        sh_raw(f, P.sh_deg, Y, col);
+        const int nb = (P.sh_deg + 1) * (P.sh_deg + 1);
+        double gc[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            c += double(gF[ch]) * fmaxf(col[ch], 0.0f);
+            gc[ch] = col[ch] > 0.0f ? wgt * gF[ch] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                if (3 * j + ch < FM) h.g[10 + 3 * j + ch] = j < nb ? static_cast<float>(gc[ch] * Y[j]) : 0.0f;
+#pragma unroll
+        for (int k = 48; k < FM; ++k) h.g[10 + k] = 0.0f;
+    } else {
+        static_assert(SH || FU == FM, "plain features: one upstream channel per feature");
+#pragma unroll
+        for (int k = 0; k < FM; ++k) {
+            const float fv = k < F ? f[k] : 0.0f;
+            c += double(gF[k]) * fv;
+        }
+#pragma unroll
+        for (int k = 0; k < FM; ++k) h.g[10 + k] = static_cast<float>(wgt * gF[k]);
+    }
     const double dA = Ti * (c - S);
     S_f = static_cast<float>(alpha * c + (1.0 - alpha) * S);
 
-#pragma unroll
-    for (int k = 0; k < FM; ++k) h.g[10 + k] = static_cast<float>(wgt * gF[k]);
     h.g[9] = static_cast<float>(dA * G);
 
     const double gu = -dA * alpha * u;
@@ -224,21 +250,23 @@ __device__ __forceinline__ void entry(const KBuf<K>& kb, const float* Tj, int j,
     *T = rt;
 }
 
-template <int FM>
+template <int FU>
 struct LaneUp {
-    float gO, gD, gF[FM];
+    float gO, gD, gF[FU];
     bool any;
 };
 
-template <int FM>
-__device__ __forceinline__ LaneUp<FM> load_upstream(const GradIn& gin, int64_t r, int F)
+// Upstream gradients of ray r; FO = composited channels (the g_feat stride).
+template <int FU>
+__device__ __forceinline__ LaneUp<FU> load_upstream(const GradIn& gin, int64_t r, int FO)
 {
-    LaneUp<FM> u;
+    const int F = FO;
+    LaneUp<FU> u;
     u.gO = gin.gO ? gin.gO[r] : 0.0f;
     u.gD = gin.gD ? gin.gD[r] : 0.0f;
     u.any = u.gO != 0.0f || u.gD != 0.0f;
 #pragma unroll
-    for (int k = 0; k < FM; ++k) {
+    for (int k = 0; k < FU; ++k) {
         u.gF[k] = (gin.gF && k < F) ? gin.gF[r * F + k] : 0.0f;
         u.any = u.any || u.gF[k] != 0.0f;
     }
@@ -248,9 +276,9 @@ __device__ __forceinline__ LaneUp<FM> load_upstream(const GradIn& gin, int64_t r
 // Re-march one ray (no saved list, or more hits than were saved): pass 1
 // records the state at the start of each round, pass 2 re-collects the
 // rounds last to first and walks each back to front.
-template <int K, int FM>
+template <int K, int FM, int FU, bool SH>
 __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
-                                            const Ray& ray, const LaneUp<FM>& up, const GradAcc& acc, Stack& st,
+                                            const Ray& ray, const LaneUp<FU>& up, const GradAcc& acc, Stack& st,
                                             float4* ck, int64_t ck_stride)
 {
     float S = 0.0f;
@@ -313,13 +341,13 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
             entry<K>(kb, Tj, j, &pos, &Ti);
             const int id = __float_as_int(sc.rec[pos].c.w);
             HitGrad<FM> h;
-            grad_hit<FM>(raw, P.F, id, ray, Ti, S, up.gO, up.gF, up.gD, h);
+            grad_hit<FM, FU, SH>(raw, P, id, ray, Ti, S, up.gO, up.gF, up.gD, h);
             acc.direct<FM>(id, h);
         }
     }
 }
 
-template <int K, int FM>
+template <int K, int FM, int FU, bool SH>
 __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                         const float* __restrict__ ro, const float* __restrict__ rd,
                                                         OutPtrs saved, bool use_saved, GradIn gin, float* gbuf,
@@ -355,19 +383,19 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
         if (c >= chunks) break;
         const int64_t r = c * kBwdBlock + tid;
         Ray ray{};
-        LaneUp<FM> up{};
+        LaneUp<FU> up{};
         int nh = 0;
         bool stored = false;
         if (r < R) {
             ray = load_ray(ro, rd, r);
-            up = load_upstream<FM>(gin, r, P.F);
+            up = load_upstream<FU>(gin, r, SH ? 3 : P.F);
             const int nh_saved = saved.n_hits ? saved.n_hits[r] : -1;
             if (up.any && sc.n > 0 && ray_valid(ray) && nh_saved != 0) {
                 if (use_saved && nh_saved > 0 && nh_saved <= saved.H_cap) {
                     stored = true;
                     nh = nh_saved;
                 } else {
-                    bwd_remarch<K, FM>(sc, raw, P, ray, up, acc, st, myck, nthr);
+                    bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr);
                 }
             }
         }
@@ -386,7 +414,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
             int id = -1;
             if (valid) {
                 id = ids[h];
-                grad_hit<FM>(raw, P.F, id, ray, Ts[h], S, up.gO, up.gF, up.gD, hg);
+                grad_hit<FM, FU, SH>(raw, P, id, ray, Ts[h], S, up.gO, up.gF, up.gD, hg);
                 if (h < kNearHits) acc.table<FM>(id, hg);
             } else {
 #pragma unroll
@@ -437,7 +465,7 @@ __global__ void k_grad_out(int64_t n, int F, int gs, const float* __restrict__ g
     }
 }
 
-template <int K, int FM>
+template <int K, int FM, int FU, bool SH>
 hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int64_t R, const float* ro,
                      const float* rd, const OutPtrs& saved, bool use_saved, const GradIn& gin, const GradOut& go,
                      int* ovf, int ovf_slots, float* ck, hipStream_t st)
@@ -450,8 +478,8 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
     // zero the accumulator and the claim counter behind it
     hipError_t e = fill_u32(gbuf, static_cast<int64_t>(sc.n) * gs + kBwdClaimWords, 0u, st);
     if (e != hipSuccess) return e;
-    const unsigned grid = persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM>, kBwdBlock));
-    k_backward<K, FM><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf, gs, ovf,
+    const unsigned grid = persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH>, kBwdBlock));
+    k_backward<K, FM, FU, SH><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf, gs, ovf,
                                                   ovf_slots, reinterpret_cast<float4*>(ck), next_chunk);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -466,13 +494,20 @@ hipError_t launch_k(const SceneView& sc, const RawSurfels& raw, const TraceParam
                     const float* rd, const OutPtrs& saved, bool use_saved, const GradIn& gin, const GradOut& go,
                     int* ovf, int ovf_slots, float* ck, hipStream_t st)
 {
-    if (P.F <= 4) return launch_kf<K, 4>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
-    if (P.F <= 8) return launch_kf<K, 8>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
+    if constexpr (K == 16 || K == 32) {  // SH: 48 coefficient gradients, 3 upstream channels
+        if (P.sh_deg >= 0)
+            return launch_kf<K, 48, 4, true>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
+    }
+    if (P.sh_deg >= 0) return hipErrorInvalidValue;
+    if (P.F <= 4)
+        return launch_kf<K, 4, 4, false>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
+    if (P.F <= 8)
+        return launch_kf<K, 8, 8, false>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
     if constexpr (K == 16 || K == 32) {
         if (P.F <= 16)
-            return launch_kf<K, 16>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
+            return launch_kf<K, 16, 16, false>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
         if (P.F <= 64)
-            return launch_kf<K, 64>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
+            return launch_kf<K, 64, 64, false>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
     }
     return hipErrorInvalidValue;
 }

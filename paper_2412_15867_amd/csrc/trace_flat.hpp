@@ -97,22 +97,42 @@ __device__ __forceinline__ int64_t claim_slot(unsigned long long* next)
     return static_cast<int64_t>(base) + rank;
 }
 
-template <int FM, class Source>
+template <int FM, bool SH, class Source>
 __device__ __forceinline__ void write_result(const Source& src, const LaneRay& lr, float O, float D, float T,
                                              const float* acc, int nh, const Counters& ct)
 {
     const OutPtrs& out = src.out(lr);
     const int64_t r = lr.r;
-    const int F = src.view(lr).F;
+    const int FO = SH ? 3 : src.view(lr).F;  // composited channels
     out.O[r] = O;
     out.D[r] = D;
 #pragma unroll
     for (int c = 0; c < FM; ++c)
-        if (c < F) out.feat[r * F + c] = acc[c];
+        if (c < FO) out.feat[r * FO + c] = acc[c];
     if (out.T) out.T[r] = T;
     if (out.n_hits) out.n_hits[r] = nh;
     if (out.counters)
         reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
+}
+
+// Add w times the features (or, with SH, the view-dependent colour) of
+// surfel `id` to the accumulators.
+template <int FM, bool SH>
+__device__ __forceinline__ void add_features(const SceneView& sc, const TraceParams& P, const Ray& ray, int id,
+                                             float w, float* acc)
+{
+    const float* f = sc.feat + static_cast<int64_t>(id) * sc.F;
+    if constexpr (SH) {
+        float Y[16], raw[3];
+        sh_basis(ray.dx, ray.dy, ray.dz, P.sh_deg, Y);
+        sh_raw(f, P.sh_deg, Y, raw);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = fmaf(w, fmaxf(raw[c], 0.0f), acc[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < FM; ++c)
+            if (c < sc.F) acc[c] = fmaf(w, f[c], acc[c]);
+    }
 }
 
 // Per-lane deferred work carried from one k-buffer round to the next: the
@@ -151,7 +171,7 @@ struct Deferred {
     }
 };
 
-template <int K, int FM, class Source>
+template <int K, int FM, bool SH, class Source>
 __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long* next_ray, const TraceParams& P,
                                            Stack& st, Deferred dq)
 {
@@ -291,7 +311,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     kb.clear();
                     dq.reset();
                     if (src.view(lr).n <= 0 || !ray_valid(ray)) {
-                        write_result<FM>(src, lr, O, D, T, acc, nh, ct);
+                        write_result<FM, SH>(src, lr, O, D, T, acc, nh, ct);
                     } else {
                         q = slab_ray(ray);
                         cur = 0;
@@ -318,10 +338,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const float w = T * a;
                 O += w;
                 D = fmaf(w, tau, D);
-                const float* f = src.view(lr).feat + static_cast<int64_t>(id) * src.view(lr).F;
-#pragma unroll
-                for (int c = 0; c < FM; ++c)
-                    if (c < src.view(lr).F) acc[c] = fmaf(w, f[c], acc[c]);
+                add_features<FM, SH>(src.view(lr), P, ray, id, w, acc);
                 const OutPtrs& out = src.out(lr);
                 if (out.hit_ids && nh < out.H_cap) {
                     out.hit_ids[lr.r * out.H_cap + nh] = id;
@@ -331,7 +348,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 ++nh;
                 if (T < P.T_min) term = true;
             } else if (term || !round_full) {
-                write_result<FM>(src, lr, O, D, T, acc, nh, ct);
+                write_result<FM, SH>(src, lr, O, D, T, acc, nh, ct);
                 mode = kFetch;
             } else {
                 kb.clear();  // `after` is the round's last (K-th) key

@@ -36,6 +36,7 @@ SEED_MC_RAYS = 24123       # Monte Carlo surface points and directions
 SEED_UPSTREAM = 24124      # upstream gradients of the differentiable trace
 SEED_SERVING = 24125       # request stream of the serving workload
 SEED_STEP = 24126          # perturbations of the training-like step
+SEED_SH = 24127            # spherical-harmonic colour coefficients
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -258,6 +259,20 @@ def mc_rays(points: int, dirs: int, seed: int = SEED_MC_RAYS,
     d = cosine_dirs(g, nn, dirs).reshape(-1, 3)
     o = np.repeat(x + offset * nn, dirs, axis=0)
     return _f32(o), _f32(d)
+
+
+def sh_coefficients(n: int, deg: int, seed: int = SEED_SH) -> np.ndarray:
+    """RGB coefficients of a view-dependent colour, (n, 3 (deg + 1)^2) float32,
+    coefficient-major (3 j + c): the constant term U[-1.5, 1.5] per channel
+    and degree-l terms N(0, 0.2 / l), the shape of trained splatting colours
+    (a dominant base colour, weak view dependence)."""
+    g = _rng(seed)
+    nb = (deg + 1) ** 2
+    k = np.zeros((n, nb, 3))
+    k[:, 0, :] = g.uniform(-1.5, 1.5, (n, 3))
+    for l in range(1, deg + 1):
+        k[:, l * l:(l + 1) * (l + 1), :] = g.normal(0.0, 0.2 / l, (n, 2 * l + 1, 3))
+    return _f32(k.reshape(n, 3 * nb))
 
 
 def upstream(R: int, F: int, seed: int = SEED_UPSTREAM, mask_rays: int | None = None):

@@ -62,6 +62,14 @@ class TraceConfig:
     brute_force: bool = False
     recompute: bool = False      # backward: re-march instead of storing hit lists
     hit_cap: int = 64            # hits stored per ray for the backward (store mode)
+    sh: bool = False             # features are RGB SH coefficients (view-dependent colour, 3 channels)
+
+    def flags(self) -> int:
+        return _lib.FLAG_SH if self.sh else 0
+
+    def out_channels(self, F: int) -> int:
+        """Composited feature channels for a scene with F features."""
+        return 3 if self.sh else F
 
 
 class Scene:
@@ -207,8 +215,8 @@ def trace(scene: Scene, ro: torch.Tensor, rd: torch.Tensor, cfg: Optional[TraceC
     hit_cap hit ids and the transmittance before each."""
     cfg = cfg or TraceConfig(**kw)
     R = _rays(scene, ro, rd)
-    res = out or alloc_result(R, scene.F, scene.device, hit_cap, counters=counters)
-    flags = _lib.FLAG_BRUTE_FORCE if cfg.brute_force else 0
+    res = out or alloc_result(R, cfg.out_channels(scene.F), scene.device, hit_cap, counters=counters)
+    flags = (_lib.FLAG_BRUTE_FORCE if cfg.brute_force else 0) | cfg.flags()
     p = scene.params(cfg, flags)
     o = res.out_struct()
     with torch.cuda.device(scene.device):
@@ -232,10 +240,10 @@ def trace_backward(scene: Scene, ro, rd, saved: TraceResult, g_opacity=None, g_f
                      scale=torch.zeros_like(scene.scale), opacity=torch.zeros_like(scene.opacity),
                      feat=torch.zeros_like(scene.feat))
     gi = []
-    for t, name, shape in ((g_opacity, "g_opacity", (R,)), (g_feat, "g_feat", (R, scene.F)),
+    for t, name, shape in ((g_opacity, "g_opacity", (R,)), (g_feat, "g_feat", (R, cfg.out_channels(scene.F))),
                            (g_depth, "g_depth", (R,))):
         gi.append(None if t is None else _req(t, name, shape, device=dev))
-    flags = _lib.FLAG_RECOMPUTE if cfg.recompute else 0
+    flags = (_lib.FLAG_RECOMPUTE if cfg.recompute else 0) | cfg.flags()
     p = scene.params(cfg, flags)
     o = saved.out_struct()
     g_in = _lib.GradIn(*(None if t is None else t.data_ptr() for t in gi))
@@ -286,6 +294,8 @@ def trace_packed(scenes: Sequence[Scene], items: Sequence[tuple], cfg: Optional[
         raise ValueError("no scenes")
     dev = scenes[0].device
     Fmax = max(s.F for s in scenes)
+    if cfg.sh:
+        raise ValueError("view-dependent SH colour is not supported by the packed launch")
     p = _lib.Params(int(cfg.k), Fmax, scenes[0].alpha_min, float(cfg.T_min), float(cfg.t_min),
                     float(cfg.t_max), scenes[0].support_sigma, 0, 0)
     handles = (ctypes.c_void_p * len(scenes))(*[s.handle.value for s in scenes])
