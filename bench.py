@@ -89,23 +89,25 @@ def calibration_copy(nbytes: int = 512 << 20, reps: int = 3):
     log(f"calibration copy: {reps} x {nbytes} bytes")
 
 
-def fwd_bytes(n_hits: np.ndarray, F: int) -> float:
+def fwd_bytes(n_hits: np.ndarray, F: int, FO: int | None = None) -> float:
     """Algorithmic bytes of a forward trace: per ray the ray (24 B), the
-    outputs (4 (2 + F) B) and one surfel record (40 + 4F B) per composited
-    hit."""
+    outputs (4 (2 + FO) B, FO composited channels) and one surfel record
+    (40 + 4F B) per composited hit."""
+    FO = F if FO is None else FO
     R = n_hits.size
-    return float(R * (24 + 4 * (2 + F)) + n_hits.astype(np.float64).sum() * (40 + 4 * F))
+    return float(R * (24 + 4 * (2 + FO)) + n_hits.astype(np.float64).sum() * (40 + 4 * F))
 
 
-def bwd_bytes(n_hits: np.ndarray, F: int) -> float:
+def bwd_bytes(n_hits: np.ndarray, F: int, FO: int | None = None) -> float:
     """Algorithmic bytes of the backward: per ray the ray, the upstream
     gradients, the saved outputs, and per hit the surfel's parameters read and
     their gradient written."""
+    FO = F if FO is None else FO
     R = n_hits.size
-    return float(R * (24 + 4 * (2 + F) + 4 * (2 + F) + 4) + n_hits.astype(np.float64).sum() * 2 * (40 + 4 * F))
+    return float(R * (24 + 4 * (2 + FO) + 4 * (2 + FO) + 4) + n_hits.astype(np.float64).sum() * 2 * (40 + 4 * F))
 
 
-def cpu_baseline(sc, ro, rd, gO, gF, gD, budget_s: float = 12.0):
+def cpu_baseline(sc, ro, rd, gO, gF, gD, budget_s: float = 12.0, sh_deg: int = -1):
     """The FP64 oracle (brute-force forward + autograd gradient over its own
     hit lists) on a seeded sample of the rays, sized to about `budget_s`."""
     import oracle
@@ -117,18 +119,18 @@ def cpu_baseline(sc, ro, rd, gO, gF, gD, budget_s: float = 12.0):
     for m in (64, 320):
         probe = np.sort(g.choice(ro.shape[0], m, replace=False))
         t0 = time.perf_counter()
-        oracle.trace(sc.astuple(), ro[probe], rd[probe], hit_cap=8)
+        oracle.trace(sc.astuple(), ro[probe], rd[probe], hit_cap=8, sh_deg=sh_deg)
         tp.append(time.perf_counter() - t0)
     per_ray = max((tp[1] - tp[0]) / 256, 1e-9)
     n = int(max(256, min(65536, budget_s / per_ray)))
     idx = np.sort(g.choice(ro.shape[0], n, replace=False))
     t0 = time.perf_counter()
-    r = oracle.trace(sc.astuple(), ro[idx], rd[idx], hit_cap=512)
+    r = oracle.trace(sc.astuple(), ro[idx], rd[idx], hit_cap=512, sh_deg=sh_deg)
     t1 = time.perf_counter()
     H = 512
     lists = np.where(np.arange(H)[None, :] < r["n_hits"][:, None], r["hits"], -1)
     lists = lists[:, :max(1, int(r["n_hits"].max()))]
-    ograd.grad_given_hits(sc.astuple(), ro[idx], rd[idx], lists, gO[idx], gF[idx], gD[idx])
+    ograd.grad_given_hits(sc.astuple(), ro[idx], rd[idx], lists, gO[idx], gF[idx], gD[idx], sh_deg=sh_deg)
     t2 = time.perf_counter()
     return dict(value=round(n / (t2 - t0) / 1e6, 9), unit="Mrays/s", cores=int(threads), kind="oracle",
                 sample=f"{n} of the {ro.shape[0]} rays (seeded), brute force over all {sc.n} surfels, FP64 "
@@ -153,9 +155,13 @@ def run_c3(args):
     dev = torch.device("cuda:0")
     N = args.surfels
     sc, ro, rd = gen_surface_workload(N, args.points, args.dirs)
+    sh = args.sh_deg >= 0
+    if sh:  # view-dependent colour: RGB SH coefficients instead of the plain features
+        sc = synth.Surfels(sc.mu, sc.quat, sc.scale, sc.opac, synth.sh_coefficients(N, args.sh_deg))
     R = ro.shape[0]
     F = sc.F
-    gO, gF, gD, _ = synth.upstream(R, F)
+    FO = 3 if sh else F
+    gO, gF, gD, _ = synth.upstream(R, FO)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     params = [t(a).requires_grad_(True) for a in sc.astuple()]
     ro_d, rd_d = t(ro), t(rd)
@@ -167,7 +173,7 @@ def run_c3(args):
     build_ms = (time.perf_counter() - b0) * 1e3
     scene.set_params(*params)
     info = scene.info()
-    cfg = TraceConfig(k=args.k, recompute=args.recompute, hit_cap=args.hit_cap)
+    cfg = TraceConfig(k=args.k, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh)
     log(f"built LBVH in {build_ms:.1f} ms, depth {info['max_depth']}; cfg {cfg}")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -204,8 +210,8 @@ def run_c3(args):
     torch.cuda.synchronize()
     n_hits = res.n_hits.cpu().numpy()
     H = float(n_hits.mean())
-    fb = fwd_bytes(n_hits, F)
-    bb = bwd_bytes(n_hits, F)
+    fb = fwd_bytes(n_hits, F, FO)
+    bb = bwd_bytes(n_hits, F, FO)
     # pure forward kernel timing (no hit-list stores) for the forward-only rate
     fo = []
     for _ in range(3):
@@ -222,7 +228,8 @@ def run_c3(args):
     dom_bytes = fb if dom_is_fwd else bb
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     line = {
-        "metric": "Mrays/s fwd+bwd @1M surfels (refit + forward + backward per step)",
+        "metric": "Mrays/s fwd+bwd @1M surfels (refit + forward + backward per step)" +
+                  (f", SH degree {args.sh_deg} colour" if sh else ""),
         "value": round(R / (step_ms * 1e-3) / 1e6, 3),
         "unit": "Mrays/s",
         "n_gpus": 1,
@@ -234,7 +241,8 @@ def run_c3(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{N} surfels (8 spheres + 4 planes, F={F}), {args.points}x{args.dirs} "
+        "config": {"workload": f"{N} surfels (8 spheres + 4 planes, F={F}"
+                               f"{f' = RGB SH degree {args.sh_deg}' if sh else ''}), {args.points}x{args.dirs} "
                                f"cosine MC rays = {R}, refit+fwd+bwd, k={args.k}, T_min=1e-4, "
                                f"{'recompute' if args.recompute else 'store'} mode",
                    "surfels": N, "rays": R, "features": F, "k": args.k},
@@ -249,13 +257,14 @@ def run_c3(args):
         "roofline": {"bound": "hbm", "kernel": "k_trace (forward)" if dom_is_fwd else "k_backward",
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic() if dom_is_fwd else None,
+                     "traffic": measured_traffic() if dom_is_fwd and not sh else None,
                      "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": round(dom_ms, 3)},
         "roofline_fwd": {"achieved": round(fb / (fwd_only_ms * 1e-3) / 1e9, 3), "bytes": fb},
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample")
-        line["cpu_baseline"] = cpu_baseline(sc, ro, rd, gO, gF, gD, budget_s=args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(sc, ro, rd, gO, gF, gD, budget_s=args.cpu_budget,
+                                            sh_deg=args.sh_deg)
     scene.close()
     return line
 
@@ -476,6 +485,8 @@ def main():
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--hit-cap", type=int, default=256)
     ap.add_argument("--recompute", action="store_true")
+    ap.add_argument("--sh-deg", type=int, default=-1,
+                    help="default workload with view-dependent colour: RGB SH coefficients of this degree (0..3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
