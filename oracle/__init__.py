@@ -18,6 +18,9 @@ code with the HIP library and never calls it.
                      max(Y(d).k + 1/2, 0) (3 output channels).
 * ``grad``        -- (submodule) FP64 autograd gradients over a given hit list
                      and central finite differences.
+* ``shade``       -- (submodule) the Monte Carlo rendering-equation consumer
+                     of the trace (Eq. 15 with Eq. 13-14 and Eq. 4): stratified
+                     hemisphere directions, cubemap lookup, shading, gradients.
 
 Inputs may be FP32 arrays; they are widened to FP64 exactly.
 """
