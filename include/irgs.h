@@ -222,6 +222,61 @@ irgs_status irgs_scene_export(irgs_scene scene, int32_t* order, int32_t* nodes, 
 
 irgs_status irgs_scene_destroy(irgs_scene scene);
 
+/* ---- Monte Carlo rendering-equation consumer of the trace (Sec. 3.3,
+ * "Rendering": Eq. 15 with the light decomposition of Eq. 13-14 and the
+ * BRDF of Eq. 4).  Per pixel p, N = S_t * S_p incident directions; ray
+ * p * N + i carries sample i of pixel p. */
+
+/* Rays of stratified uniform hemisphere sampling: sample i = s * S_p + t has
+ * cos(theta) = (s + u[p][i][0]) / S_t, phi = 2 pi (t + u[p][i][1]) / S_p in
+ * the frame (t1, t2, n_p), (t1, t2) the branchless orthonormal basis of
+ * Duff et al. 2017 (t1 = (1 + s nx^2 a, s b, -s nx), t2 = (b, s + ny^2 a,
+ * -ny), s = sign(nz) with sign(0) = 1, a = -1 / (s + nz), b = nx ny a).
+ * Origin x_p + offset n_p.  x, n: P x 3 (n unit); u: P x N x 2 uniforms;
+ * ro, rd: (P N) x 3 written.  S_t, S_p >= 1; P >= 0. */
+irgs_status irgs_mc_rays(int64_t P, int32_t S_t, int32_t S_p, const float* x, const float* n, const float* u,
+                         float offset, float* ro, float* rd, void* stream);
+
+/* Shading inputs (DEVICE pointers, borrowed). */
+typedef struct {
+    int64_t P;            /* pixels */
+    int32_t N;            /* samples per pixel */
+    int32_t E;            /* cubemap face resolution (E x E texels) */
+    const float* n;       /* P x 3 unit normals */
+    const float* wo;      /* P x 3 unit directions towards the viewer */
+    const float* albedo;  /* P x 3 diffuse albedo a */
+    const float* rough;   /* P roughness r */
+    const float* wi;      /* P x N x 3 incident directions (the rays' rd) */
+    const float* O;       /* P x N opacity of each ray's trace (V = 1 - O) */
+    const float* Lind;    /* P x N x 3 colour of each ray's trace (L_ind) */
+    const float* env;     /* 6 x E x E x 3 cubemap L_dir: faces +x, -x, +y, -y, +z, -z */
+} irgs_shade_in;
+
+/* c[p] = 2 pi / N sum_i (a / pi + f_s) (V_i L_dir(w_i) + L_ind,i) (w_i . n),
+ * f_s = D F G / (4 (w_i . n)(w_o . n)): D GGX with alpha = r^2, F Schlick
+ * with F0 = 0.04, G Smith with Schlick-GGX G1 and k = (r + 1)^2 / 8; both
+ * cosines clamped below at 1e-4 inside G and the denominator.  L_dir is the
+ * nearest texel: major axis picks the face (ties to x, then y), face
+ * coordinates (s, t) = (-z, -y)/|x|, (z, -y)/|x|, (x, z)/|y|, (x, -z)/|y|,
+ * (x, -y)/|z|, (-x, -y)/|z|, texel row floor((t + 1) E / 2), column
+ * floor((s + 1) E / 2), clamped.  c: P x 3 written. */
+irgs_status irgs_mc_shade(const irgs_shade_in* in, float* c, void* stream);
+
+/* Gradients of sum(g_c * c) (g_c: P x 3): albedo (P x 3), rough (P) and env
+ * (6 x E x E x 3) are accumulated (+=, caller zeroes; env by atomics); O
+ * (P x N) and Lind (P x N x 3) are written -- they are the upstream
+ * gradients of the trace's opacity and colour for irgs_trace_backward.  Any
+ * pointer may be NULL (skipped). */
+typedef struct {
+    float* albedo;
+    float* rough;
+    float* env;
+    float* O;
+    float* Lind;
+} irgs_shade_grads;
+irgs_status irgs_mc_shade_backward(const irgs_shade_in* in, const float* g_c, irgs_shade_grads* grads,
+                                   void* stream);
+
 const char* irgs_status_str(irgs_status status);
 const char* irgs_last_error(void);
 const char* irgs_version(void);

@@ -69,9 +69,11 @@ def stratified_dirs(n, u, S_t: int, S_p: int):
     return loc[0][..., None] * t1[:, None, :] + loc[1][..., None] * t2[:, None, :] + loc[2][..., None] * n[:, None, :]
 
 
-def cube_texel(d, E: int):
-    """(face, row, col) of the nearest texel of each direction d (..., 3)."""
-    d = np.asarray(d, np.float64)
+def cube_texel(d, E: int, dtype=np.float64):
+    """(face, row, col) of the nearest texel of each direction d (..., 3).
+    The texel is an integer decided by floating point: parity checks against
+    an FP32 kernel take the decision in float32 (dtype) like the kernel."""
+    d = np.asarray(d, dtype)
     ax = np.abs(d)
     major = np.argmax(ax, -1)  # ties go to the lower axis (x, then y)
     x, y, z = d[..., 0], d[..., 1], d[..., 2]
@@ -81,8 +83,9 @@ def cube_texel(d, E: int):
     s = np.select([face == 0, face == 1, face == 2, face == 3, face == 4, face == 5], [-z, z, x, x, x, -x])
     t = np.select([face == 0, face == 1, face == 2, face == 3, face == 4, face == 5], [-y, -y, z, -z, -y, -y])
     s, t = s / m, t / m
-    col = np.clip(np.floor((s + 1.0) * E / 2.0), 0, E - 1).astype(np.int64)
-    row = np.clip(np.floor((t + 1.0) * E / 2.0), 0, E - 1).astype(np.int64)
+    one, half, e = dtype(1.0), dtype(0.5), dtype(E)
+    col = np.clip(np.floor((s + one) * e * half), 0, E - 1).astype(np.int64)
+    row = np.clip(np.floor((t + one) * e * half), 0, E - 1).astype(np.int64)
     return face, row, col
 
 
@@ -117,21 +120,21 @@ def _brdf_spec(n, wo, wi, r, lib):
     return fs, ndl
 
 
-def shade(n, wo, albedo, rough, wi, O, Lind, env):
+def shade(n, wo, albedo, rough, wi, O, Lind, env, texel_dtype=np.float64):
     """c_pbr (P, 3), FP64 numpy.  wi (P, N, 3), O (P, N), Lind (P, N, 3),
     env (6, E, E, 3)."""
     n, wo, albedo, rough, wi, O, Lind, env = (np.asarray(a, np.float64) for a in
                                                 (n, wo, albedo, rough, wi, O, Lind, env))
     N, E = wi.shape[1], env.shape[1]
     fs, ndl = _brdf_spec(n, wo, wi, rough, np)
-    f, row, col = cube_texel(wi, E)
+    f, row, col = cube_texel(wi, E, texel_dtype)
     Ldir = env[f, row, col]                                      # (P, N, 3)
     Li = (1.0 - O)[..., None] * Ldir + Lind
     brdf = albedo[:, None, :] / np.pi + fs[..., None]
     return 2.0 * np.pi / N * (brdf * Li * ndl[..., None]).sum(1)
 
 
-def shade_grad(n, wo, albedo, rough, wi, O, Lind, env, g_c):
+def shade_grad(n, wo, albedo, rough, wi, O, Lind, env, g_c, texel_dtype=np.float64):
     """FP64 autograd gradients of sum(g_c * c_pbr) with respect to albedo,
     roughness, the cubemap, O and L_ind."""
     t = lambda a: torch.tensor(np.asarray(a, np.float64))
@@ -140,7 +143,7 @@ def shade_grad(n, wo, albedo, rough, wi, O, Lind, env, g_c):
     E = env_t.shape[1]
     N = wi_t.shape[1]
     fs, ndl = _brdf_spec(n_t, wo_t, wi_t, rough_t, torch)
-    f, row, col = cube_texel(np.asarray(wi, np.float64), E)
+    f, row, col = cube_texel(np.asarray(wi, np.float64), E, texel_dtype)
     Ldir = env_t[torch.tensor(f), torch.tensor(row), torch.tensor(col)]
     Li = (1.0 - O_t)[..., None] * Ldir + Lind_t
     brdf = albedo_t[:, None, :] / np.pi + fs[..., None]

@@ -52,6 +52,15 @@ class Work(ctypes.Structure):
                 ("ro", c_vp), ("rd", c_vp), ("out", Out)]
 
 
+class ShadeIn(ctypes.Structure):
+    _fields_ = [("P", c_i64), ("N", c_i32), ("E", c_i32), ("n", c_vp), ("wo", c_vp), ("albedo", c_vp),
+                ("rough", c_vp), ("wi", c_vp), ("O", c_vp), ("Lind", c_vp), ("env", c_vp)]
+
+
+class ShadeGrads(ctypes.Structure):
+    _fields_ = [("albedo", c_vp), ("rough", c_vp), ("env", c_vp), ("O", c_vp), ("Lind", c_vp)]
+
+
 # name -> (restype, argtypes); the exported symbols of include/irgs.h
 SIGNATURES = {
     "irgs_scene_bytes": (ctypes.c_size_t, [c_i64, c_i32]),
@@ -68,6 +77,9 @@ SIGNATURES = {
     "irgs_scene_info": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i32)]),
     "irgs_scene_export": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "irgs_scene_destroy": (ctypes.c_int, [c_vp]),
+    "irgs_mc_rays": (ctypes.c_int, [c_i64, c_i32, c_i32, c_vp, c_vp, c_vp, c_f32, c_vp, c_vp, c_vp]),
+    "irgs_mc_shade": (ctypes.c_int, [ctypes.POINTER(ShadeIn), c_vp, c_vp]),
+    "irgs_mc_shade_backward": (ctypes.c_int, [ctypes.POINTER(ShadeIn), c_vp, ctypes.POINTER(ShadeGrads), c_vp]),
     "irgs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "irgs_last_error": (ctypes.c_char_p, []),
     "irgs_version": (ctypes.c_char_p, []),

@@ -247,6 +247,49 @@ extern "C" {
 
 const char* irgs_version(void) { return "irgs-gfx950 0.1"; }
 
+irgs_status irgs_mc_rays(int64_t P, int32_t S_t, int32_t S_p, const float* x, const float* n, const float* u,
+                         float offset, float* ro, float* rd, void* stream)
+{
+    if (P < 0 || S_t < 1 || S_p < 1) return fail(IRGS_E_INVALID, "P >= 0, S_t >= 1 and S_p >= 1 required");
+    if (P > 0 && (!x || !n || !u || !ro || !rd)) return fail(IRGS_E_INVALID, "NULL pointer");
+    if (!std::isfinite(offset)) return fail(IRGS_E_INVALID, "offset must be finite");
+    const hipError_t e = launch_mc_rays(P, S_t, S_p, x, n, u, offset, ro, rd, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "mc rays launch");
+}
+
+static irgs_status check_shade(const irgs_shade_in* in, ShadeArgs* a)
+{
+    if (!in) return fail(IRGS_E_INVALID, "shade inputs are NULL");
+    if (in->P < 0 || in->N < 1 || in->E < 1) return fail(IRGS_E_INVALID, "P >= 0, N >= 1 and E >= 1 required");
+    if (in->P > 0 && (!in->n || !in->wo || !in->albedo || !in->rough || !in->wi || !in->O || !in->Lind || !in->env))
+        return fail(IRGS_E_INVALID, "NULL shade input");
+    *a = ShadeArgs{in->P, in->N, in->E, in->n, in->wo, in->albedo, in->rough, in->wi, in->O, in->Lind, in->env};
+    return IRGS_OK;
+}
+
+irgs_status irgs_mc_shade(const irgs_shade_in* in, float* c, void* stream)
+{
+    ShadeArgs a;
+    const irgs_status st = check_shade(in, &a);
+    if (st != IRGS_OK) return st;
+    if (a.P > 0 && !c) return fail(IRGS_E_INVALID, "c is NULL");
+    const hipError_t e = launch_mc_shade(a, c, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "shade launch");
+}
+
+irgs_status irgs_mc_shade_backward(const irgs_shade_in* in, const float* g_c, irgs_shade_grads* grads,
+                                   void* stream)
+{
+    ShadeArgs a;
+    const irgs_status st = check_shade(in, &a);
+    if (st != IRGS_OK) return st;
+    if (!grads) return fail(IRGS_E_INVALID, "grads is NULL");
+    if (a.P > 0 && !g_c) return fail(IRGS_E_INVALID, "g_c is NULL");
+    const ShadeGrads g{grads->albedo, grads->rough, grads->env, grads->O, grads->Lind};
+    const hipError_t e = launch_mc_shade_backward(a, g_c, g, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "shade backward launch");
+}
+
 const char* irgs_last_error(void) { return g_err.c_str(); }
 
 const char* irgs_status_str(irgs_status s)

@@ -149,6 +149,34 @@ struct WorkItem {
 hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_rays,
                          const TraceParams& P, int k, const FlatScratch& fs, int grid_blocks, hipStream_t st);
 
+// Monte Carlo rendering-equation consumer (shade.hip).
+struct ShadeArgs {
+    int64_t P;            // pixels
+    int32_t N;            // samples per pixel
+    int32_t E;            // cubemap face resolution
+    const float* n;       // P x 3
+    const float* wo;      // P x 3
+    const float* albedo;  // P x 3
+    const float* rough;   // P
+    const float* wi;      // P x N x 3
+    const float* O;       // P x N
+    const float* Lind;    // P x N x 3
+    const float* env;     // 6 x E x E x 3
+};
+
+struct ShadeGrads {
+    float* albedo;  // P x 3, accumulated
+    float* rough;   // P, accumulated
+    float* env;     // 6 x E x E x 3, accumulated
+    float* O;       // P x N, written
+    float* Lind;    // P x N x 3, written
+};
+
+hipError_t launch_mc_rays(int64_t P, int St, int Sp, const float* x, const float* n, const float* u, float offset,
+                          float* ro, float* rd, hipStream_t st);
+hipError_t launch_mc_shade(const ShadeArgs& a, float* c, hipStream_t st);
+hipError_t launch_mc_shade_backward(const ShadeArgs& a, const float* g_c, const ShadeGrads& g, hipStream_t st);
+
 // Fill n 32-bit words with v (a kernel, so it can be captured in a graph).
 hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);
 
