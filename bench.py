@@ -11,7 +11,9 @@ bwd)), with per-phase timings, the roofline of the dominant kernel measured
 live with HIP events, and the FP64 oracle timed on the host for a bounded
 sample of the same workload.
 
-Other workloads (--workload): c1 (4,096-surfel cube, 64x64 camera rays) and
+Other workloads (--workload): pbr (the rendering-equation step: 1,024
+pixels x 256 stratified directions on the 1M-surfel scene, SH colour, cubemap
+sky, refit + trace + shading + backward), c1 (4,096-surfel cube, 64x64 camera rays) and
 c2 (200K surfels, 4.2M MC rays), forward only against the brute-force GPU
 tracer; serve (three
 resident scenes, Poisson request stream, packed launches vs one launch per
@@ -471,12 +473,82 @@ def run_c5(args):
     return line
 
 
+def run_pbr(args):
+    """Rendering-equation step (Sec. 3.3 "Rendering", Eq. 13-15): P pixels of
+    the 1M-surfel scene, N = 16 x 16 stratified directions each (the paper's
+    N_r = 256), view-dependent SH colour of degree 3 in the trace, a 32 x 32
+    cubemap sky; per step refit, rays, differentiable trace, shading, and the
+    backward through shading and trace to surfels, materials and sky."""
+    import torch
+    from paper_2412_15867_amd import Scene, TraceConfig, render_pbr, synth, trace, mc_rays
+    dev = torch.device("cuda:0")
+    N_surf, P, St, Sp = args.surfels, args.pixels, 16, 16
+    Nr = St * Sp
+    lay = synth.layout()
+    sc = synth.surface_scene(N_surf, F=8, lay=lay)
+    surf = synth.Surfels(sc.mu, sc.quat, sc.scale, sc.opac, synth.sh_coefficients(N_surf, 3))
+    px = synth.shading_pixels(P, Nr, lay=lay)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    params = [t(a).requires_grad_(True) for a in surf.astuple()]
+    mats = [t(px[k]).requires_grad_(True) for k in ("albedo", "rough", "env")]
+    x, n, wo, u = (t(px[k]) for k in ("x", "n", "wo", "u"))
+    g_c = torch.from_numpy(np.random.default_rng(synth.SEED_PBR + 1).standard_normal((P, 3)).astype(np.float32)).to(dev)
+    scene = Scene(*[p.detach() for p in params])
+    scene.set_params(*params)
+    cfg = TraceConfig(k=args.k, sh=True, hit_cap=args.hit_cap)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step():
+        for q in params + mats:
+            q.grad = None
+        e = [ev() for _ in range(4)]
+        e[0].record()
+        scene.refit()
+        e[1].record()
+        c = render_pbr(scene, params, x, n, wo, *mats, u, St, Sp, cfg)
+        e[2].record()
+        (c * g_c).sum().backward()
+        e[3].record()
+        return e
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    med = lambda i, j: float(np.median([e[i].elapsed_time(e[j]) for e in evs]))
+    R = P * Nr
+    ro, rd = mc_rays(x, n, u, St, Sp)
+    res = trace(scene, ro, rd, cfg, hit_cap=0)
+    torch.cuda.synchronize()
+    nh = res.n_hits.cpu().numpy()
+    fwd_ms = med(1, 2)
+    fb = fwd_bytes(nh, surf.F, 3)
+    line = {"metric": "Mrays/s rendering-equation step (refit + rays + trace + shading + backward)",
+            "value": round(R / (step_ms * 1e-3) / 1e6, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{N_surf} surfels (8 spheres + 4 planes, SH degree 3 colour), {P} pixels x "
+                                   f"{St}x{Sp} stratified directions = {R} rays, 32x32 cubemap, k={args.k}, "
+                                   "T_min=1e-4, store mode", "pixels": P, "rays": R},
+            "refit_ms": round(med(0, 1), 3), "render_fwd_ms": round(fwd_ms, 3), "bwd_ms": round(med(2, 3), 3),
+            "hits_per_ray": round(float(nh.mean()), 3),
+            "roofline": {"bound": "hbm", "kernel": "rays + k_trace + shading (forward)",
+                         "achieved": round(fb / (fwd_ms * 1e-3) / 1e9, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(fb / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None}}
+    scene.close()
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "serve", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "serve", "c5", "pbr"])
+    ap.add_argument("--pixels", type=int, default=1024, help="pbr workload: pixels (x 256 directions)")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--surfels", type=int, default=1_000_000)
@@ -503,6 +575,8 @@ def main():
         line = run_forward_only(args, small=args.workload == "c1")
     elif args.workload == "serve":
         line = run_serve(args)
+    elif args.workload == "pbr":
+        line = run_pbr(args)
     else:
         line = run_c5(args)
     if args.calibrate_copy:

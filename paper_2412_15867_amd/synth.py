@@ -37,6 +37,7 @@ SEED_UPSTREAM = 24124      # upstream gradients of the differentiable trace
 SEED_SERVING = 24125       # request stream of the serving workload
 SEED_STEP = 24126          # perturbations of the training-like step
 SEED_SH = 24127            # spherical-harmonic colour coefficients
+SEED_PBR = 24128           # pixels, materials, sky and sampling uniforms of the shading workload
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -259,6 +260,25 @@ def mc_rays(points: int, dirs: int, seed: int = SEED_MC_RAYS,
     d = cosine_dirs(g, nn, dirs).reshape(-1, 3)
     o = np.repeat(x + offset * nn, dirs, axis=0)
     return _f32(o), _f32(d)
+
+
+def shading_pixels(P: int, N: int, E: int = 32, seed: int = SEED_PBR, lay: Layout | None = None):
+    """Inputs of the rendering-equation workload: P area-uniform surface
+    points x with normals n (planes: random side), view directions w_o
+    uniform over the hemisphere of n, albedo U[0,1]^3, roughness U[0.1, 1],
+    a (6, E, E, 3) cubemap sky U[0, 3] and the (P, N, 2) sampling uniforms.
+    All float32."""
+    if lay is None:
+        lay = layout()
+    g = _rng(seed)
+    x, nn, sid = _sample_surface(g, lay, P)
+    flip = np.where((sid >= 8) & (g.random(P) < 0.5), -1.0, 1.0)
+    nn = nn * flip[:, None]
+    wo = _unit(g.standard_normal((P, 3)))
+    wo = np.where(((wo * nn).sum(1) < 0)[:, None], -wo, wo)
+    return dict(x=_f32(x), n=_f32(nn), wo=_f32(wo), albedo=_f32(g.uniform(0, 1, (P, 3))),
+                rough=_f32(g.uniform(0.1, 1.0, P)), env=_f32(g.uniform(0, 3, (6, E, E, 3))),
+                u=_f32(g.uniform(0, 1, (P, N, 2))))
 
 
 def sh_coefficients(n: int, deg: int, seed: int = SEED_SH) -> np.ndarray:
