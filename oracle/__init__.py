@@ -11,6 +11,8 @@ code with the HIP library and never calls it.
                      (t_min, t_max), with its FP64 depth, u^2+v^2 and alpha.
 * ``replay``      -- FP64 compositing of a given ordered hit list.
 * ``frames``      -- tangent frame (t_u, t_v, n) of each quaternion.
+* ``with_normal``  -- (trace / replay option) 3 more composited channels: each
+                     hit's unit normal turned to face the ray (relighting).
 * ``sh_basis``    -- real spherical-harmonic basis of directions (degree <= 3),
                      by the associated-Legendre recurrence; with ``sh_deg`` >= 0
                      ``trace`` / ``replay`` read the features as RGB SH
@@ -36,13 +38,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trace_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-DEFAULTS = dict(alpha_min=1.0 / 255.0, T_min=1e-4, t_min=0.0, t_max=float("inf"), sigma=3.0, sh_deg=-1)
+DEFAULTS = dict(alpha_min=1.0 / 255.0, T_min=1e-4, t_min=0.0, t_max=float("inf"), sigma=3.0, sh_deg=-1,
+                with_normal=0)
 
 
 class Params(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_double), ("T_min", ctypes.c_double),
                 ("t_min", ctypes.c_double), ("t_max", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("sh_deg", ctypes.c_int32)]
+                ("sh_deg", ctypes.c_int32), ("with_normal", ctypes.c_int32)]
 
 
 def build(force: bool = True) -> str:
@@ -72,7 +75,7 @@ def lib():
                                      P, P, P, P, P, P, i32]
         L.orc_candidates.restype = ctypes.c_int
         L.orc_replay.argtypes = [i64, i32, P, P, P, P, P, i64, P, P, i32, P, P,
-                                 P, P, P, P, P, P, P, i32, i32]
+                                 P, P, P, P, P, P, P, i32, i32, i32]
         L.orc_replay.restype = ctypes.c_int
         L.orc_sh_basis.argtypes = [i64, P, i32, P]
         L.orc_sh_basis.restype = None
@@ -95,7 +98,8 @@ def _p(a: np.ndarray):
 def make_params(**kw) -> Params:
     d = dict(DEFAULTS)
     d.update({k: v for k, v in kw.items() if k in d})
-    return Params(d["alpha_min"], d["T_min"], d["t_min"], d["t_max"], d["sigma"], int(d["sh_deg"]))
+    return Params(d["alpha_min"], d["T_min"], d["t_min"], d["t_max"], d["sigma"], int(d["sh_deg"]),
+                  int(bool(d["with_normal"])))
 
 
 def out_channels(F: int, sh_deg: int) -> int:
@@ -125,7 +129,7 @@ def trace(surfels, ro, rd, hit_cap: int = 0, nthreads: int = 0, **kw):
     N, F, R = mu.shape[0], feat.shape[1], ro.shape[0]
     O, D, T = np.zeros(R), np.zeros(R), np.ones(R)
     prm = make_params(**kw)
-    Fo = np.zeros((R, out_channels(F, prm.sh_deg)))
+    Fo = np.zeros((R, out_channels(F, prm.sh_deg) + (3 if prm.with_normal else 0)))
     nh = np.zeros(R, dtype=np.int32)
     hits = np.full((R, max(hit_cap, 1)), -1, dtype=np.int32)
     rc = lib().orc_trace(N, F, _p(mu), _p(quat), _p(scale), _p(opac), _p(feat), R, _p(ro), _p(rd),
@@ -157,7 +161,7 @@ def candidates(surfels, ro, rd, cap: int = 512, band: float = 1e-2, nthreads: in
     return dict(ids=ids, tau=tau, rho2=rho2, alpha=alpha, hit=hit.astype(bool), count=cnt)
 
 
-def replay(surfels, ro, rd, lists, lengths, nthreads: int = 0, sh_deg: int = -1):
+def replay(surfels, ro, rd, lists, lengths, nthreads: int = 0, sh_deg: int = -1, with_normal: bool = False):
     """Composite the given ordered lists (R, H) int32 of length `lengths`."""
     mu, quat, scale, opac, feat = _surfels(surfels)
     ro, rd = _d(ro).reshape(-1, 3), _d(rd).reshape(-1, 3)
@@ -166,13 +170,13 @@ def replay(surfels, ro, rd, lists, lengths, nthreads: int = 0, sh_deg: int = -1)
     N, F, R = mu.shape[0], feat.shape[1], ro.shape[0]
     H = lists.shape[1]
     O, D, T = np.zeros(R), np.zeros(R), np.ones(R)
-    Fo = np.zeros((R, out_channels(F, sh_deg)))
+    Fo = np.zeros((R, out_channels(F, sh_deg) + (3 if with_normal else 0)))
     Tpost = np.ones((R, H))
     tau = np.zeros((R, H))
     alpha = np.zeros((R, H))
     lib().orc_replay(N, F, _p(mu), _p(quat), _p(scale), _p(opac), _p(feat), R, _p(ro), _p(rd), H,
                      _p(lists), _p(lengths), _p(O), _p(Fo), _p(D), _p(T), _p(Tpost), _p(tau), _p(alpha),
-                     int(sh_deg), nthreads)
+                     int(sh_deg), int(bool(with_normal)), nthreads)
     return dict(O=O, F=Fo, D=D, T=T, Tpost=Tpost, tau=tau, alpha=alpha)
 
 

@@ -42,6 +42,11 @@
  * offset and the clamp at 0 are those of the Gaussian-splatting colour
  * model; the composited feature output then has 3 channels.
  *
+ * Normal channels (relighting: the trace blends albedo, roughness and the
+ * normal): with with_normal = 1 each hit also contributes its unit normal
+ * n, negated when n . r_d > 0 so that it faces the ray, as 3 more channels
+ * after the features.
+ *
  * All inputs are FP64 (callers widen FP32 data exactly).  OpenMP over rays.
  */
 #include <math.h>
@@ -60,6 +65,7 @@ typedef struct {
     double t_max;
     double sigma; /* support radius in units of the scales */
     int32_t sh_deg; /* -1: plain features; 0..3: RGB SH coefficients */
+    int32_t with_normal; /* 1: 3 more channels, each hit's unit normal turned to face the ray */
 } orc_params;
 
 typedef struct {
@@ -176,6 +182,13 @@ void orc_sh_basis(int64_t n, const double* dirs, int32_t deg, double* Y)
     for (int64_t i = 0; i < n; ++i) sh_basis(dirs + 3 * i, deg, Y + i * nb);
 }
 
+/* Unit normal of surfel S turned to face the ray direction d. */
+static void facing_normal(const orc_surfel* S, const double* d, double* out)
+{
+    const double s = dot3(S->n, d) > 0.0 ? -1.0 : 1.0;
+    for (int k = 0; k < 3; ++k) out[k] = s * S->n[k];
+}
+
 /* Colour of one surfel seen along the ray whose basis is Y (3 channels). */
 static void sh_colour(const double* k, int deg, const double* Y, double* col)
 {
@@ -273,7 +286,8 @@ int orc_trace(int64_t N, int32_t F, const double* mu, const double* quat, const 
             const double* o_r = ro + 3 * r;
             const double* d_r = rd + 3 * r;
             double acc_O = 0.0, acc_D = 0.0, trans = 1.0;
-            const int FO = P->sh_deg >= 0 ? 3 : F;
+            const int FC = P->sh_deg >= 0 ? 3 : F;
+            const int FO = FC + (P->with_normal ? 3 : 0);
             double* acc_F = Fo + (size_t)r * FO;
             for (int c = 0; c < FO; ++c) acc_F[c] = 0.0;
             double Y[16];
@@ -315,6 +329,11 @@ int orc_trace(int64_t N, int32_t F, const double* mu, const double* quat, const 
                     for (int c = 0; c < 3; ++c) acc_F[c] += w * col[c];
                 } else {
                     for (int c = 0; c < F; ++c) acc_F[c] += w * f[c];
+                }
+                if (P->with_normal) {
+                    double nf[3];
+                    facing_normal(&S[buf[h].id], d_r, nf);
+                    for (int c = 0; c < 3; ++c) acc_F[FC + c] += w * nf[c];
                 }
                 acc_D += w * buf[h].tau;
                 trans *= (1.0 - buf[h].alpha);
@@ -383,18 +402,20 @@ int orc_candidates(int64_t N, const double* mu, const double* quat, const double
 int orc_replay(int64_t N, int32_t F, const double* mu, const double* quat, const double* scale,
                const double* opac, const double* feat, int64_t R, const double* ro, const double* rd,
                int32_t H, const int32_t* list, const int32_t* len, double* O, double* Fo, double* D, double* T,
-               double* Tpost, double* tau_out, double* alpha_out, int32_t sh_deg, int32_t nthreads)
+               double* Tpost, double* tau_out, double* alpha_out, int32_t sh_deg, int32_t with_normal,
+               int32_t nthreads)
 {
     orc_surfel* S = build_surfels(N, mu, quat, scale, opac);
     if (!S) return -1;
     set_threads(nthreads);
-    orc_params loose = {0.0, 0.0, -INFINITY, INFINITY, INFINITY, sh_deg};
+    orc_params loose = {0.0, 0.0, -INFINITY, INFINITY, INFINITY, sh_deg, with_normal};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < R; ++r) {
         const double* o_r = ro + 3 * r;
         const double* d_r = rd + 3 * r;
         double acc_O = 0.0, acc_D = 0.0, trans = 1.0;
-        const int FO = sh_deg >= 0 ? 3 : F;
+        const int FC = sh_deg >= 0 ? 3 : F;
+        const int FO = FC + (with_normal ? 3 : 0);
         double* acc_F = Fo + (size_t)r * FO;
         for (int c = 0; c < FO; ++c) acc_F[c] = 0.0;
         double Y[16];
@@ -413,6 +434,11 @@ int orc_replay(int64_t N, int32_t F, const double* mu, const double* quat, const
                 for (int c = 0; c < 3; ++c) acc_F[c] += w * col[c];
             } else {
                 for (int c = 0; c < F; ++c) acc_F[c] += w * f[c];
+            }
+            if (with_normal && id >= 0 && id < N) {
+                double nf[3];
+                facing_normal(&S[id], d_r, nf);
+                for (int c = 0; c < 3; ++c) acc_F[FC + c] += w * nf[c];
             }
             acc_D += w * t;
             trans *= (1.0 - a);
