@@ -99,6 +99,13 @@ typedef struct {
  * normalised ray direction.  out->feat and grad_in->g_feat are then R x 3;
  * grads->feat stays N x F.  k must be 16 or 32; not for irgs_trace_packed. */
 #define IRGS_FLAG_SH 4u
+/* trace only (relighting: the trace alpha-blends albedo, roughness and the
+ * normal): after the F <= 5 features, 3 more composited channels hold each
+ * hit's unit normal, negated where it points along the ray (n . r_d > 0) so
+ * that it faces the ray; out->feat is R x (F + 3).  Exclusive with
+ * IRGS_FLAG_SH; k must be 16 or 32; not for the backward or the packed
+ * launch. */
+#define IRGS_FLAG_NORMAL 8u
 
 /* Outputs of a trace, caller-allocated (R = number of rays):
  *   opacity (R)      accumulated opacity O = sum T_i alpha_i (o_rt of Eq. 8;
@@ -276,6 +283,39 @@ typedef struct {
 } irgs_shade_grads;
 irgs_status irgs_mc_shade_backward(const irgs_shade_in* in, const float* g_c, irgs_shade_grads* grads,
                                    void* stream);
+
+/* ---- Relighting variant (the paper's relighting details): the trace with
+ * IRGS_FLAG_NORMAL blends albedo (3), roughness (1) and the ray-facing
+ * normal with weights T_i alpha_i (normalised here by O), and each ray's
+ * indirect radiance is shaded in one query with the split-sum
+ * approximation; the result feeds irgs_mc_shade as L_ind. */
+
+/* Pre-integrated sky (DEVICE buffers): irr (6 x E x E x 3) = irradiance
+ * sum_w L(w) max(w . c, 0) dOmega(w) at every texel centre c (NULL: skip);
+ * pref (M x 6 x E x E x 3) = the sky prefiltered with the GGX lobe of
+ * roughness r_l = (l + 1) / M around c (normal = view = c):
+ * sum L(w) D_r(c . h) max(w . c, 0) dOmega / the same sum without L,
+ * h = normalise(w + c).  Texel centres and solid angles
+ * 4 / (E^2 (1 + s^2 + t^2)^{3/2}) follow the cube addressing of
+ * irgs_mc_shade.  1 <= E <= 256, 0 <= M <= 32. */
+irgs_status irgs_env_prefilter(int32_t E, const float* env, int32_t M, float* irr, float* pref, void* stream);
+
+/* Split-sum BRDF table (S x S x 2, DEVICE) at cell centres
+ * (n.v, r) = ((i + 1/2)/S, (j + 1/2)/S): (S_A, S_B) estimated with GGX
+ * importance sampling over 256 Hammersley points ((k + 1/2)/256, bit-reversed
+ * k / 2^32); per sample with n.l > 0, g = G (v.h) / ((n.h)(n.v)),
+ * F_c = (1 - v.h)^5, S_A += (1 - F_c) g, S_B += F_c g; G as in
+ * irgs_mc_shade.  1 <= S <= 1024. */
+irgs_status irgs_brdf_table(int32_t S, float* table, void* stream);
+
+/* Indirect radiance (R x 3, written) of each ray from its trace outputs O (R)
+ * and Fo (R x 7: albedo, roughness, normal channels of IRGS_FLAG_NORMAL):
+ * A = Fo[0:3] / O, R = clamp(Fo[3] / O, 0, 1), N = normalise(Fo[4:7]), v = -d,
+ * L_ind = A / pi E(N) + P_R(reflect(d, N)) (0.04 S_A(n.v, R) + S_B(n.v, R))
+ * with nearest texel, level clamp(floor(R M + 1/2) - 1, 0, M - 1) and table
+ * cell (floor(n.v S), floor(R S)); 0 for a ray with O = 0. */
+irgs_status irgs_relight_lind(int64_t R, const float* O, const float* Fo, const float* rd, int32_t E, const float* irr,
+                              int32_t M, const float* pref, int32_t S, const float* table, float* lind, void* stream);
 
 const char* irgs_status_str(irgs_status status);
 const char* irgs_last_error(void);

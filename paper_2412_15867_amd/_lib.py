@@ -22,6 +22,7 @@ IRGS_E_STATE = -4
 FLAG_BRUTE_FORCE = 1
 FLAG_RECOMPUTE = 2
 FLAG_SH = 4          # features are RGB SH coefficients; 3 composited channels
+FLAG_NORMAL = 8      # 3 more composited channels: the ray-facing normal (forward only)
 
 
 class Surfels(ctypes.Structure):
@@ -78,6 +79,9 @@ SIGNATURES = {
     "irgs_scene_export": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "irgs_scene_destroy": (ctypes.c_int, [c_vp]),
     "irgs_mc_rays": (ctypes.c_int, [c_i64, c_i32, c_i32, c_vp, c_vp, c_vp, c_f32, c_vp, c_vp, c_vp]),
+    "irgs_env_prefilter": (ctypes.c_int, [c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "irgs_brdf_table": (ctypes.c_int, [c_i32, c_vp, c_vp]),
+    "irgs_relight_lind": (ctypes.c_int, [c_i64, c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "irgs_mc_shade": (ctypes.c_int, [ctypes.POINTER(ShadeIn), c_vp, c_vp]),
     "irgs_mc_shade_backward": (ctypes.c_int, [ctypes.POINTER(ShadeIn), c_vp, ctypes.POINTER(ShadeGrads), c_vp]),
     "irgs_status_str": (ctypes.c_char_p, [ctypes.c_int]),

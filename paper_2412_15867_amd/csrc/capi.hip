@@ -120,6 +120,11 @@ irgs_status check_params(const irgs_params* p, int32_t F)
             return fail(IRGS_E_INVALID, "IRGS_FLAG_SH needs 3 (deg + 1)^2 features, deg <= 3 (3, 12, 27, 48); F = %d", F);
         if (k != 16 && k != 32) return fail(IRGS_E_INVALID, "IRGS_FLAG_SH supports k = 16 or 32");
     }
+    if (p->flags & IRGS_FLAG_NORMAL) {
+        if (p->flags & IRGS_FLAG_SH) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL and IRGS_FLAG_SH are exclusive");
+        if (F > 5) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL supports F <= 5 (got %d)", F);
+        if (k != 16 && k != 32) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL supports k = 16 or 32");
+    }
     return IRGS_OK;
 }
 
@@ -223,6 +228,7 @@ TraceParams trace_params(const irgs_params* p, int32_t F)
     t.T_min = p->T_min;
     t.F = F;
     t.sh_deg = (p->flags & IRGS_FLAG_SH) ? sh_degree(F) : -1;
+    t.normals = (p->flags & IRGS_FLAG_NORMAL) ? 1 : 0;
     return t;
 }
 
@@ -275,6 +281,31 @@ irgs_status irgs_mc_shade(const irgs_shade_in* in, float* c, void* stream)
     if (a.P > 0 && !c) return fail(IRGS_E_INVALID, "c is NULL");
     const hipError_t e = launch_mc_shade(a, c, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? IRGS_OK : hip_fail(e, "shade launch");
+}
+
+irgs_status irgs_env_prefilter(int32_t E, const float* env, int32_t M, float* irr, float* pref, void* stream)
+{
+    if (E < 1 || E > 256 || M < 0 || M > 32) return fail(IRGS_E_INVALID, "1 <= E <= 256 and 0 <= M <= 32 required");
+    if (!env || (!irr && !pref) || (M > 0 && !pref)) return fail(IRGS_E_INVALID, "NULL pointer");
+    const hipError_t e = launch_env_prefilter(E, env, M, irr, pref, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "prefilter launch");
+}
+
+irgs_status irgs_brdf_table(int32_t S, float* table, void* stream)
+{
+    if (S < 1 || S > 1024 || !table) return fail(IRGS_E_INVALID, "1 <= S <= 1024 and a table are required");
+    const hipError_t e = launch_brdf_table(S, table, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "table launch");
+}
+
+irgs_status irgs_relight_lind(int64_t R, const float* O, const float* Fo, const float* rd, int32_t E, const float* irr,
+                              int32_t M, const float* pref, int32_t S, const float* table, float* lind, void* stream)
+{
+    if (R < 0 || E < 1 || M < 1 || S < 1) return fail(IRGS_E_INVALID, "R >= 0, E, M, S >= 1 required");
+    if (R > 0 && (!O || !Fo || !rd || !irr || !pref || !table || !lind)) return fail(IRGS_E_INVALID, "NULL pointer");
+    const RelightArgs a{R, O, Fo, rd, E, M, S, irr, pref, table};
+    const hipError_t e = launch_relight_lind(a, lind, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "relight launch");
 }
 
 irgs_status irgs_mc_shade_backward(const irgs_shade_in* in, const float* g_c, irgs_shade_grads* grads,
@@ -442,6 +473,7 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
 {
     irgs_status st = check_trace_common(s, p, R, ro, rd);
     if (st != IRGS_OK) return st;
+    if (p->flags & IRGS_FLAG_NORMAL) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL is forward-only (relighting)");
     if (!saved || !gin || !grads) return fail(IRGS_E_INVALID, "saved, grad_in and grads are required");
     if (R > 0 && !saved->n_hits) return fail(IRGS_E_INVALID, "saved->n_hits is required");
     if (R == 0 || s->n == 0) return IRGS_OK;
@@ -470,7 +502,8 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
     if (!p) return fail(IRGS_E_INVALID, "params is NULL");
     if (n_items < 0 || (n_items > 0 && !items)) return fail(IRGS_E_INVALID, "bad items");
     if (p->k != 16 && p->k != 32) return fail(IRGS_E_INVALID, "packed launch supports k = 16 or 32");
-    if (p->flags & IRGS_FLAG_SH) return fail(IRGS_E_INVALID, "IRGS_FLAG_SH is not supported by the packed launch");
+    if (p->flags & (IRGS_FLAG_SH | IRGS_FLAG_NORMAL))
+        return fail(IRGS_E_INVALID, "IRGS_FLAG_SH / IRGS_FLAG_NORMAL are not supported by the packed launch");
     int32_t Fmax = 0;
     int slots = 0;
     std::vector<SceneView> views(n_scenes);

@@ -72,10 +72,19 @@ struct SceneView {
     int32_t F;
 };
 
+// How the composited channels are formed from a hit (template argument of
+// the forward kernels).
+enum ColourMode : int {
+    kColPlain = 0,   // the surfel's F features
+    kColSH = 1,      // view-dependent colour from RGB SH coefficients (3 channels)
+    kColNormal = 2,  // the F features, then the unit normal turned to face the ray (F + 3)
+};
+
 struct TraceParams {
     float t_min, t_max, T_min;
     int32_t F;       // features per surfel
     int32_t sh_deg;  // -1: features composited as they are; 0..3: RGB SH coefficients (3 output channels)
+    int32_t normals; // 1: the features, then the ray-facing unit normal (F + 3 output channels)
 };
 
 struct Ray {

@@ -177,6 +177,22 @@ hipError_t launch_mc_rays(int64_t P, int St, int Sp, const float* x, const float
 hipError_t launch_mc_shade(const ShadeArgs& a, float* c, hipStream_t st);
 hipError_t launch_mc_shade_backward(const ShadeArgs& a, const float* g_c, const ShadeGrads& g, hipStream_t st);
 
+// Relighting variant (relight.hip).
+struct RelightArgs {
+    int64_t R;
+    const float* O;      // R
+    const float* Fo;     // R x 7: blended albedo (3), roughness, normal (3), all times O
+    const float* rd;     // R x 3
+    int32_t E, M, S;     // cube resolution, prefilter levels, table size
+    const float* irr;    // 6 x E x E x 3
+    const float* pref;   // M x 6 x E x E x 3
+    const float* table;  // S x S x 2
+};
+
+hipError_t launch_env_prefilter(int E, const float* env, int M, float* irr, float* pref, hipStream_t st);
+hipError_t launch_brdf_table(int S, float* table, hipStream_t st);
+hipError_t launch_relight_lind(const RelightArgs& a, float* lind, hipStream_t st);
+
 // Fill n 32-bit words with v (a kernel, so it can be captured in a graph).
 hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);
 

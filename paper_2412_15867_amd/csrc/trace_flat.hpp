@@ -97,13 +97,14 @@ __device__ __forceinline__ int64_t claim_slot(unsigned long long* next)
     return static_cast<int64_t>(base) + rank;
 }
 
-template <int FM, bool SH, class Source>
+template <int FM, int CM, class Source>
 __device__ __forceinline__ void write_result(const Source& src, const LaneRay& lr, float O, float D, float T,
                                              const float* acc, int nh, const Counters& ct)
 {
     const OutPtrs& out = src.out(lr);
     const int64_t r = lr.r;
-    const int FO = SH ? 3 : src.view(lr).F;  // composited channels
+    const int F = src.view(lr).F;
+    const int FO = CM == kColSH ? 3 : (CM == kColNormal ? F + 3 : F);  // composited channels
     out.O[r] = O;
     out.D[r] = D;
 #pragma unroll
@@ -115,14 +116,15 @@ __device__ __forceinline__ void write_result(const Source& src, const LaneRay& l
         reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
 }
 
-// Add w times the features (or, with SH, the view-dependent colour) of
-// surfel `id` to the accumulators.
-template <int FM, bool SH>
+// Add w times the features (with SH: the view-dependent colour; with the
+// normal mode: the features, then the record's unit normal `nr` turned to
+// face the ray) of surfel `id` to the accumulators.
+template <int FM, int CM>
 __device__ __forceinline__ void add_features(const SceneView& sc, const TraceParams& P, const Ray& ray, int id,
-                                             float w, float* acc)
+                                             const float4& nr, float w, float* acc)
 {
     const float* f = sc.feat + static_cast<int64_t>(id) * sc.F;
-    if constexpr (SH) {
+    if constexpr (CM == kColSH) {
         float Y[16], raw[3];
         sh_basis(ray.dx, ray.dy, ray.dz, P.sh_deg, Y);
         sh_raw(f, P.sh_deg, Y, raw);
@@ -132,6 +134,13 @@ __device__ __forceinline__ void add_features(const SceneView& sc, const TracePar
 #pragma unroll
         for (int c = 0; c < FM; ++c)
             if (c < sc.F) acc[c] = fmaf(w, f[c], acc[c]);
+        if constexpr (CM == kColNormal) {
+            const float s = dot3(nr.x, nr.y, nr.z, ray.dx, ray.dy, ray.dz) > 0.0f ? -w : w;
+            const float nv[3] = {nr.x, nr.y, nr.z};
+#pragma unroll
+            for (int c = 0; c < FM; ++c)
+                if (c >= sc.F && c < sc.F + 3) acc[c] = fmaf(s, nv[c - sc.F], acc[c]);
+        }
     }
 }
 
@@ -171,7 +180,7 @@ struct Deferred {
     }
 };
 
-template <int K, int FM, bool SH, class Source>
+template <int K, int FM, int CM, class Source>
 __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long* next_ray, const TraceParams& P,
                                            Stack& st, Deferred dq)
 {
@@ -311,7 +320,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     kb.clear();
                     dq.reset();
                     if (src.view(lr).n <= 0 || !ray_valid(ray)) {
-                        write_result<FM, SH>(src, lr, O, D, T, acc, nh, ct);
+                        write_result<FM, CM>(src, lr, O, D, T, acc, nh, ct);
                     } else {
                         q = slab_ray(ray);
                         cur = 0;
@@ -338,7 +347,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const float w = T * a;
                 O += w;
                 D = fmaf(w, tau, D);
-                add_features<FM, SH>(src.view(lr), P, ray, id, w, acc);
+                add_features<FM, CM>(src.view(lr), P, ray, id, s.b, w, acc);
                 const OutPtrs& out = src.out(lr);
                 if (out.hit_ids && nh < out.H_cap) {
                     out.hit_ids[lr.r * out.H_cap + nh] = id;
@@ -348,7 +357,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 ++nh;
                 if (T < P.T_min) term = true;
             } else if (term || !round_full) {
-                write_result<FM, SH>(src, lr, O, D, T, acc, nh, ct);
+                write_result<FM, CM>(src, lr, O, D, T, acc, nh, ct);
                 mode = kFetch;
             } else {
                 kb.clear();  // `after` is the round's last (K-th) key

@@ -26,7 +26,7 @@ int64_t trace_threads(int64_t R)
 
 namespace {
 
-template <int K, int FM, bool BVH, bool SH>
+template <int K, int FM, bool BVH, int CM>
 __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams& P, const Ray& ray, int64_t r,
                                           const OutPtrs& out, Stack& st)
 {
@@ -58,7 +58,7 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
                     const float w = T * a;
                     O += w;
                     D = fmaf(w, tau, D);
-                    add_features<FM, SH>(sc, P, ray, id, w, acc);
+                    add_features<FM, CM>(sc, P, ray, id, s.b, w, acc);
                     if (out.hit_ids && nh < out.H_cap) {
                         out.hit_ids[r * out.H_cap + nh] = id;
                         if (out.hit_T) out.hit_T[r * out.H_cap + nh] = T;
@@ -76,7 +76,7 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
     }
     out.O[r] = O;
     out.D[r] = D;
-    const int FO = SH ? 3 : P.F;  // composited channels
+    const int FO = CM == kColSH ? 3 : (CM == kColNormal ? P.F + 3 : P.F);  // composited channels
 #pragma unroll
     for (int c = 0; c < FM; ++c)
         if (c < FO) out.feat[r * FO + c] = acc[c];
@@ -86,7 +86,7 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
         reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
 }
 
-template <int K, int FM, bool BVH, bool SH>
+template <int K, int FM, bool BVH, int CM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 && FM <= 8 ? 4 : 1))) void k_trace(SceneView sc, TraceParams P, int64_t R,
                                                   const float* __restrict__ ro, const float* __restrict__ rd,
                                                   OutPtrs out, FlatScratch fs)
@@ -99,16 +99,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 
     if (BVH) {
         const PlainSource src{sc, out, ro, rd, R};
         Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
-        trace_flat<K, FM, SH>(src, fs.next_ray, P, st, dq);
+        trace_flat<K, FM, CM>(src, fs.next_ray, P, st, dq);
     } else {
         for (int64_t r = gtid; r < R; r += nthr) {
             const Ray ray = load_ray(ro, rd, r);
-            trace_one<K, FM, false, SH>(sc, P, ray, r, out, st);
+            trace_one<K, FM, false, CM>(sc, P, ray, r, out, st);
         }
     }
 }
 
-template <int K, int FM, bool BVH, bool SH>
+template <int K, int FM, bool BVH, int CM>
 hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
                      const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
 {
@@ -116,8 +116,8 @@ hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const
         const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
         if (e != hipSuccess) return e;
     }
-    const unsigned grid = persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH, SH>, kBlock));
-    k_trace<K, FM, BVH, SH><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, fs);
+    const unsigned grid = persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH, CM>, kBlock));
+    k_trace<K, FM, BVH, CM><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, fs);
     return hipGetLastError();
 }
 
@@ -126,14 +126,18 @@ hipError_t launch_k(const SceneView& sc, const TraceParams& P, int64_t R, const 
                     const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
 {
     if constexpr (K == 16 || K == 32) {
-        if (P.sh_deg >= 0) return launch_kf<K, 4, BVH, true>(sc, P, R, ro, rd, out, fs, st);  // 3 colour channels
+        if (P.sh_deg >= 0) return launch_kf<K, 4, BVH, kColSH>(sc, P, R, ro, rd, out, fs, st);  // 3 colour channels
+        if (P.normals) {
+            if (P.F <= 5) return launch_kf<K, 8, BVH, kColNormal>(sc, P, R, ro, rd, out, fs, st);  // F + 3 channels
+            return hipErrorInvalidValue;
+        }
     }
-    if (P.sh_deg >= 0) return hipErrorInvalidValue;
-    if (P.F <= 4) return launch_kf<K, 4, BVH, false>(sc, P, R, ro, rd, out, fs, st);
-    if (P.F <= 8) return launch_kf<K, 8, BVH, false>(sc, P, R, ro, rd, out, fs, st);
+    if (P.sh_deg >= 0 || P.normals) return hipErrorInvalidValue;
+    if (P.F <= 4) return launch_kf<K, 4, BVH, kColPlain>(sc, P, R, ro, rd, out, fs, st);
+    if (P.F <= 8) return launch_kf<K, 8, BVH, kColPlain>(sc, P, R, ro, rd, out, fs, st);
     if constexpr (K == 16 || K == 32) {
-        if (P.F <= 16) return launch_kf<K, 16, BVH, false>(sc, P, R, ro, rd, out, fs, st);
-        if (P.F <= 64) return launch_kf<K, 64, BVH, false>(sc, P, R, ro, rd, out, fs, st);
+        if (P.F <= 16) return launch_kf<K, 16, BVH, kColPlain>(sc, P, R, ro, rd, out, fs, st);
+        if (P.F <= 64) return launch_kf<K, 64, BVH, kColPlain>(sc, P, R, ro, rd, out, fs, st);
     }
     return hipErrorInvalidValue;
 }
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__
              static_cast<int>(threadIdx.x), 0, kStackLds};
     const PackedSource src{scenes, items, n_items, n_rays};
     Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
-    trace_flat<K, FM, false>(src, fs.next_ray, P, st, dq);
+    trace_flat<K, FM, kColPlain>(src, fs.next_ray, P, st, dq);
 }
 
 template <int K, int FM>

@@ -9,7 +9,11 @@ in libirgs.so.
     O, F, _ = TraceFn.apply(*params, ro, rd, scene, cfg)  # visibility, L_ind
     c = ShadeFn.apply(albedo, rough, env, O.view(P, N), F.view(P, N, 3), n, wo, rd.view(P, N, 3))
 
-or ``render_pbr(...)`` for the three together.
+or ``render_pbr(...)`` for the three together.  Relighting (forward only):
+``env_prefilter`` / ``brdf_table`` pre-integrate the sky and the BRDF,
+``relight_lind`` shades each ray's blended albedo / roughness / normal
+(a trace with ``TraceConfig(normals=True)``) with the split-sum
+approximation, and ``relight(...)`` chains rays, trace, that and Eq. 15.
 """
 from __future__ import annotations
 
@@ -109,3 +113,61 @@ def render_pbr(scene: Scene, params, x, n, wo, albedo, rough, env, u, S_t: int, 
     if F.shape[1] != 3:
         raise ValueError("render_pbr needs a 3-channel trace colour")
     return ShadeFn.apply(albedo, rough, env, O.view(P, N), F.view(P, N, 3), n, wo, rd.view(P, N, 3))
+
+
+# ---- relighting variant (forward only) -------------------------------------
+
+def env_prefilter(env: torch.Tensor, M: int = 8):
+    """Irradiance (6, E, E, 3) and GGX-prefiltered skies (M, 6, E, E, 3) of
+    the cubemap env (6, E, E, 3), roughness levels (l + 1) / M."""
+    E = env.shape[1]
+    _req(env, "env", (6, E, E, 3), device=env.device)
+    irr = torch.empty_like(env)
+    pref = torch.empty((M, 6, E, E, 3), dtype=torch.float32, device=env.device)
+    with torch.cuda.device(env.device):
+        check(_lib.lib().irgs_env_prefilter(E, _ptr(env), int(M), _ptr(irr), _ptr(pref), _stream_handle(env.device)),
+              "irgs_env_prefilter")
+    return irr, pref
+
+
+def brdf_table(S: int = 32, device=None) -> torch.Tensor:
+    """Split-sum table (S, S, 2) at cell centres (n.v, roughness)."""
+    device = device or torch.device("cuda:0")
+    t = torch.empty((S, S, 2), dtype=torch.float32, device=device)
+    with torch.cuda.device(device):
+        check(_lib.lib().irgs_brdf_table(int(S), _ptr(t), _stream_handle(device)), "irgs_brdf_table")
+    return t
+
+
+def relight_lind(O, Fo, rd, irr, pref, table) -> torch.Tensor:
+    """Split-sum indirect radiance (R, 3) of each ray from the trace outputs
+    of IRGS_FLAG_NORMAL (O (R), Fo (R, 7) = albedo, roughness, normal)."""
+    R = O.shape[0]
+    dev = O.device
+    E, M, S = irr.shape[1], pref.shape[0], table.shape[0]
+    for t, name, shape in ((O, "O", (R,)), (Fo, "Fo", (R, 7)), (rd, "rd", (R, 3)), (irr, "irr", (6, E, E, 3)),
+                           (pref, "pref", (M, 6, E, E, 3)), (table, "table", (S, S, 2))):
+        _req(t, name, shape, device=dev)
+    out = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    with torch.cuda.device(dev):
+        check(_lib.lib().irgs_relight_lind(R, _ptr(O), _ptr(Fo), _ptr(rd), E, _ptr(irr), M, _ptr(pref), S,
+                                           _ptr(table), _ptr(out), _stream_handle(dev)), "irgs_relight_lind")
+    return out
+
+
+def relight(scene: Scene, x, n, wo, albedo, rough, env, u, S_t: int, S_p: int, irr=None, pref=None, table=None,
+            k: int = 16, T_min: float = 1e-4, offset: float = 1e-3):
+    """Relit colour (P, 3) under the sky env: stratified rays, the trace
+    blending each ray's albedo, roughness and normal (the scene's 4 features
+    are albedo and roughness), split-sum indirect radiance, Eq. 15."""
+    from .tracer import trace
+    if irr is None or pref is None:
+        irr, pref = env_prefilter(env)
+    if table is None:
+        table = brdf_table(device=env.device)
+    P = x.shape[0]
+    N = int(S_t) * int(S_p)
+    ro, rd = mc_rays(x, n, u, S_t, S_p, offset)
+    res = trace(scene, ro, rd, TraceConfig(k=k, T_min=T_min, normals=True))
+    lind = relight_lind(res.opacity, res.feat, rd, irr, pref, table)
+    return shade(n, wo, albedo, rough, rd.view(P, N, 3), res.opacity.view(P, N), lind.view(P, N, 3), env)

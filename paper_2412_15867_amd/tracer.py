@@ -63,13 +63,14 @@ class TraceConfig:
     recompute: bool = False      # backward: re-march instead of storing hit lists
     hit_cap: int = 64            # hits stored per ray for the backward (store mode)
     sh: bool = False             # features are RGB SH coefficients (view-dependent colour, 3 channels)
+    normals: bool = False        # forward only: 3 more channels, the ray-facing normal (relighting)
 
     def flags(self) -> int:
-        return _lib.FLAG_SH if self.sh else 0
+        return (_lib.FLAG_SH if self.sh else 0) | (_lib.FLAG_NORMAL if self.normals else 0)
 
     def out_channels(self, F: int) -> int:
         """Composited feature channels for a scene with F features."""
-        return 3 if self.sh else F
+        return 3 if self.sh else F + (3 if self.normals else 0)
 
 
 class Scene:
@@ -294,8 +295,8 @@ def trace_packed(scenes: Sequence[Scene], items: Sequence[tuple], cfg: Optional[
         raise ValueError("no scenes")
     dev = scenes[0].device
     Fmax = max(s.F for s in scenes)
-    if cfg.sh:
-        raise ValueError("view-dependent SH colour is not supported by the packed launch")
+    if cfg.sh or cfg.normals:
+        raise ValueError("SH colour and normal channels are not supported by the packed launch")
     p = _lib.Params(int(cfg.k), Fmax, scenes[0].alpha_min, float(cfg.T_min), float(cfg.t_min),
                     float(cfg.t_max), scenes[0].support_sigma, 0, 0)
     handles = (ctypes.c_void_p * len(scenes))(*[s.handle.value for s in scenes])

@@ -29,7 +29,7 @@ TIE_REL = 1e-6
 
 
 def validate(surfels, ro, rd, gpu, rays=None, T_min=1e-4, alpha_min=1.0 / 255.0, sigma=3.0, t_min=0.0,
-             t_max=np.inf, atol=1e-4, cap=4096, term_band=1e-4, sh_deg=-1):
+             t_max=np.inf, atol=1e-4, cap=4096, term_band=1e-4, sh_deg=-1, with_normal=False):
     """Returns a stats dict; raises AssertionError with a message on the
     first failing ray.  `gpu` holds numpy arrays O, F, D, T, n_hits, hit_ids."""
     ro = np.asarray(ro, np.float64)
@@ -42,14 +42,15 @@ def validate(surfels, ro, rd, gpu, rays=None, T_min=1e-4, alpha_min=1.0 / 255.0,
     sub_ro, sub_rd = ro[rays], rd[rays]
     cand = oracle.candidates(surfels, sub_ro, sub_rd, cap=cap, band=0.05, T_min=T_min, alpha_min=alpha_min,
                              sigma=sigma, t_min=t_min, t_max=t_max)
-    ref = oracle.trace(surfels, sub_ro, sub_rd, hit_cap=cap, T_min=T_min, alpha_min=alpha_min, sigma=sigma, sh_deg=sh_deg,
+    ref = oracle.trace(surfels, sub_ro, sub_rd, hit_cap=cap, T_min=T_min, alpha_min=alpha_min, sigma=sigma, sh_deg=sh_deg, with_normal=with_normal,
                        t_min=t_min, t_max=t_max)
     H = gpu["hit_ids"].shape[1]
     nh = gpu["n_hits"][rays]
     assert np.all(nh <= H), "hit list capacity too small for validation"
     lists = np.ascontiguousarray(gpu["hit_ids"][rays])
-    rep = oracle.replay(surfels, sub_ro, sub_rd, lists, nh, sh_deg=sh_deg)
-    rep_ref = oracle.replay(surfels, sub_ro, sub_rd, ref["hits"], ref["n_hits"], sh_deg=sh_deg)
+    rep = oracle.replay(surfels, sub_ro, sub_rd, lists, nh, sh_deg=sh_deg, with_normal=with_normal)
+    rep_ref = oracle.replay(surfels, sub_ro, sub_rd, ref["hits"], ref["n_hits"], sh_deg=sh_deg,
+                            with_normal=with_normal)
     stats = dict(rays=len(rays), exact=0, exact_eligible=0, ambiguous_rays=0, tie_rays=0, hits=int(nh.sum()))
     for k, r in enumerate(rays):
         n = int(nh[k])
