@@ -13,7 +13,9 @@ sample of the same workload.
 
 Other workloads (--workload): pbr (the rendering-equation step: 1,024
 pixels x 256 stratified directions on the 1M-surfel scene, SH colour, cubemap
-sky, refit + trace + shading + backward), c1 (4,096-surfel cube, 64x64 camera rays) and
+sky, refit + trace + shading + backward), relight (the same pixels on
+albedo / roughness surfels: trace with the blended normal, split-sum indirect
+light, Eq. 15; the sky precompute timed apart), c1 (4,096-surfel cube, 64x64 camera rays) and
 c2 (200K surfels, 4.2M MC rays), forward only against the brute-force GPU
 tracer; serve (three
 resident scenes, Poisson request stream, packed launches vs one launch per
@@ -542,13 +544,89 @@ def run_pbr(args):
     return line
 
 
+def run_relight(args):
+    """Relighting step (the paper's relighting details): once per sky, the
+    irradiance and GGX-prefiltered cubemaps (32 x 32, 8 roughness levels) and
+    the 32 x 32 split-sum table; per frame, P pixels x 16 x 16 stratified
+    directions on the 1M-surfel scene whose 4 features are albedo and
+    roughness, the trace blending them with the ray-facing normal, the
+    split-sum indirect radiance per ray, and Eq. 15 (forward only)."""
+    import torch
+    from paper_2412_15867_amd import Scene, TraceConfig, synth, trace, mc_rays
+    from paper_2412_15867_amd import brdf_table, env_prefilter, relight
+    dev = torch.device("cuda:0")
+    N_surf, P, St, Sp, M, S = args.surfels, args.pixels, 16, 16, 8, 32
+    Nr = St * Sp
+    lay = synth.layout()
+    sc = synth.surface_scene(N_surf, F=4, lay=lay)
+    feat = sc.feat.copy()
+    feat[:, 3] = 0.1 + 0.9 * feat[:, 3]
+    px = synth.shading_pixels(P, Nr, lay=lay)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    scene = Scene(t(sc.mu), t(sc.quat), t(sc.scale), t(sc.opac), t(feat))
+    x, n, wo, u, albedo, rough, env = (t(px[k]) for k in ("x", "n", "wo", "u", "albedo", "rough", "env"))
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def pre():
+        e = [ev(), ev()]
+        e[0].record()
+        irr, pref = env_prefilter(env, M)
+        tab = brdf_table(S, device=dev)
+        e[1].record()
+        return (irr, pref, tab), e
+
+    def frame(tabs):
+        return relight(scene, x, n, wo, albedo, rough, env, u, St, Sp, *tabs, k=args.k)
+
+    for _ in range(args.warmup):
+        tabs, _e = pre()
+        frame(tabs)
+    torch.cuda.synchronize()
+    pre_evs = [pre()[1] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        frame(tabs)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    pre_ms = float(np.median([e[0].elapsed_time(e[1]) for e in pre_evs]))
+    R = P * Nr
+    ro, rd = mc_rays(x, n, u, St, Sp)
+    cfg = TraceConfig(k=args.k, normals=True)
+    es = [ev(), ev()]
+    es[0].record()
+    res = trace(scene, ro, rd, cfg)
+    es[1].record()
+    torch.cuda.synchronize()
+    trace_ms = es[0].elapsed_time(es[1])
+    res = trace(scene, ro, rd, cfg, hit_cap=0)
+    torch.cuda.synchronize()
+    nh = res.n_hits.cpu().numpy()
+    fb = fwd_bytes(nh, 4, 7)
+    line = {"metric": "Mrays/s relighting frame (rays + trace with blended normal + split-sum + Eq. 15)",
+            "value": round(R / (step_ms * 1e-3) / 1e6, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{N_surf} surfels (8 spheres + 4 planes; albedo + roughness features), {P} "
+                                   f"pixels x {St}x{Sp} stratified directions = {R} rays, 32x32 cubemap, {M} "
+                                   f"prefiltered levels, {S}x{S} BRDF table, k={args.k}, T_min=1e-4",
+                       "pixels": P, "rays": R},
+            "sky_precompute_ms": round(pre_ms, 3), "trace_ms": round(trace_ms, 3),
+            "hits_per_ray": round(float(nh.mean()), 3),
+            "roofline": {"bound": "hbm", "kernel": "k_trace (normal blending)",
+                         "achieved": round(fb / (trace_ms * 1e-3) / 1e9, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(fb / (trace_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None}}
+    scene.close()
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "serve", "c5", "pbr"])
-    ap.add_argument("--pixels", type=int, default=1024, help="pbr workload: pixels (x 256 directions)")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "serve", "c5", "pbr", "relight"])
+    ap.add_argument("--pixels", type=int, default=1024, help="pbr / relight workloads: pixels (x 256 directions)")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--surfels", type=int, default=1_000_000)
@@ -577,6 +655,8 @@ def main():
         line = run_serve(args)
     elif args.workload == "pbr":
         line = run_pbr(args)
+    elif args.workload == "relight":
+        line = run_relight(args)
     else:
         line = run_c5(args)
     if args.calibrate_copy:
