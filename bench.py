@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "k_trace_traffic_1M_surfels_4M_rays.md")
 CSRC = os.path.join(ROOT, "paper_2412_15867_amd", "csrc")
-FWD_SOURCES = ("trace_fwd.hip", "trace_flat.hpp", "march.hpp", "irgs_device.hpp", "irgs_internal.hpp")
+FWD_SOURCES = ("trace_fwd.hip", "trace_flat.hpp", "march.hpp", "irgs_device.hpp", "irgs_internal.hpp", "lbvh.hip")
 
 
 def log(msg):
