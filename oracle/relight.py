@@ -29,7 +29,20 @@ Readings (the paper cites the split-sum construction and gives no numbers):
   F_c = (1 - v.h)^5, S_A += (1 - F_c) g, S_B += F_c g; then / 256 (the
   table lookup takes the nearest cell);
 * texel solid angles are exact for the cube face parameterisation:
-  dOmega = 4 / (E^2 (1 + s^2 + t^2)^{3/2}) at the texel centre (s, t).
+  dOmega = 4 / (E^2 (1 + s^2 + t^2)^{3/2}) at the texel centre (s, t);
+* importance sampling of the sky (the paper samples the known environment
+  by its intensity instead of the stratified hemisphere): intensity I = the
+  mean of the texel's RGB (clamped at 0), texel weight I dOmega at its
+  centre, the inclusive running sum of the weights in texel order
+  (face, row, col) as the CDF; a sample (u0, u1, u2) picks the first texel
+  whose CDF exceeds u0 * total (FP32, as the kernel decides it), then the
+  point (s, t) = ((col + u1), (row + u2)) 2 / E - 1 of that texel, uniform
+  in the face coordinates, so pdf(w) = p_j E^2 / 4 (1 + s^2 + t^2)^{3/2}
+  with p_j = (CDF_j - CDF_{j-1}) / total; the estimator weight is
+  1 / (N pdf) for n . w > 0 and 0 below the horizon; texels of zero
+  intensity are never drawn (their directions then carry no light of any
+  kind: an unbiased estimate needs a sky that is positive where light,
+  direct or indirect, arrives).
 """
 from __future__ import annotations
 
@@ -40,14 +53,21 @@ from .shade import F0, cube_texel, ggx_D, smith_G
 HAMMERSLEY_N = 256
 
 
+def face_point(face, s, t):
+    """Unnormalised direction of face coordinates (s, t) on a face (the
+    inverse of the nearest-texel addressing)."""
+    face, s, t = np.broadcast_arrays(np.asarray(face), np.asarray(s, np.float64), np.asarray(t, np.float64))
+    one = np.ones_like(s)
+    cand = np.stack([np.stack([one, -t, -s], -1), np.stack([-one, -t, s], -1), np.stack([s, one, t], -1),
+                     np.stack([s, -one, -t], -1), np.stack([s, -t, one], -1), np.stack([-s, -t, -one], -1)])
+    return np.take_along_axis(cand, face[None, ..., None].astype(np.int64), 0)[0]
+
+
 def texel_dirs(E: int):
     """(6, E, E, 3) unit centre directions and (E, E) solid angles."""
     c = (np.arange(E) + 0.5) / E * 2.0 - 1.0
     t, s = np.meshgrid(c, c, indexing="ij")       # row index -> t, column -> s
-    one = np.ones_like(s)
-    faces = [np.stack([one, -t, -s], -1), np.stack([-one, -t, s], -1), np.stack([s, one, t], -1),
-             np.stack([s, -one, -t], -1), np.stack([s, -t, one], -1), np.stack([-s, -t, -one], -1)]
-    d = np.stack(faces)
+    d = face_point(np.arange(6)[:, None, None], s[None], t[None])
     d = d / np.linalg.norm(d, axis=-1, keepdims=True)
     dw = 4.0 / (E * E * (1.0 + s * s + t * t) ** 1.5)
     return d, dw
@@ -160,3 +180,42 @@ def relight_lind(O, Fo, rd, irr, pref, table):
     j = np.clip(np.floor(np.clip(Rg, 0.0, 1.0) * S), 0, S - 1).astype(np.int64)
     Ls = Pr * (F0 * table[i, j, 0] + table[i, j, 1])[:, None]
     return np.where(hit[:, None], Ld + Ls, 0.0)
+
+
+def env_cdf(env):
+    """(6 E^2,) inclusive CDF of the texel weights max(mean RGB, 0) dOmega."""
+    env = np.asarray(env, np.float64)
+    E = env.shape[1]
+    _, dw = texel_dirs(E)
+    inten = np.fmax(env.mean(-1), 0.0)                       # NaN -> 0
+    return np.cumsum((inten * dw[None]).reshape(-1))
+
+
+def env_sample(x, n, u, cdf32, E: int, offset: float = 1e-3):
+    """Rays drawn from the sky's intensity: x, n (P, 3), u (P, N, 3)
+    uniforms in [0, 1), cdf32 the FP32 CDF both sides decide with.  Returns
+    ro, rd (P, N, 3) and the estimator weights (P, N): 1 / (N pdf), 0 below
+    the horizon or for a sky with no positive weight."""
+    x, n, u = (np.asarray(a, np.float64) for a in (x, n, u))
+    cdf32 = np.asarray(cdf32, np.float32)
+    P, N = u.shape[0], u.shape[1]
+    total32 = cdf32[-1]
+    target = np.float32(u[..., 0].astype(np.float32) * total32)          # FP32 product, as the kernel
+    target = np.where(target < total32, target, np.nextafter(total32, np.float32(0)))
+    j = np.minimum(np.searchsorted(cdf32, target, side="right"), cdf32.size - 1)
+    face, rc = j // (E * E), j % (E * E)
+    row, col = rc // E, rc % E
+    s = (col + u[..., 1]) * 2.0 / E - 1.0
+    t = (row + u[..., 2]) * 2.0 / E - 1.0
+    d = face_point(face, s, t)
+    d = d / np.linalg.norm(d, axis=-1, keepdims=True)
+    cdf = cdf32.astype(np.float64)
+    total = float(total32)
+    pj = (cdf[j] - np.where(j > 0, cdf[np.maximum(j - 1, 0)], 0.0)) / (total if total > 0 else 1.0)
+    pdf = pj * E * E / 4.0 * (1.0 + s * s + t * t) ** 1.5
+    up = (d * n[:, None, :]).sum(-1) > 0
+    ok = up & (pdf > 0) & (total > 0)
+    wgt = np.where(ok, 1.0 / (N * np.where(ok, pdf, 1.0)), 0.0)
+    ro = np.broadcast_to(x[:, None, :] + offset * n[:, None, :], d.shape)
+    return ro, d, wgt
+

@@ -9,6 +9,10 @@ the camera, albedo a, roughness r) and its N_r = S_t * S_p incident
 directions w_i:
 
     c_pbr = 2 pi / N_r * sum_i (f_d + f_s(w_i)) L_i(w_i) (w_i . n)      (Eq. 15)
+
+(2 pi / N_r = 1 / (N_r pdf) of the uniform hemisphere; with another
+sampling density each sample carries its own weight 1 / (N_r pdf(w_i)),
+0 below the horizon, which the relighting variant uses)
     L_i   = V_i L_dir(w_i) + L_ind,i,  V_i = 1 - O_i                    (Eq. 13-14)
     f_d   = a / pi,  f_s = D F G / (4 (w_i . n)(w_o . n))               (Eq. 4)
 
@@ -120,23 +124,26 @@ def _brdf_spec(n, wo, wi, r, lib):
     return fs, ndl
 
 
-def shade(n, wo, albedo, rough, wi, O, Lind, env, texel_dtype=np.float64):
+def shade(n, wo, albedo, rough, wi, O, Lind, env, texel_dtype=np.float64, wgt=None):
     """c_pbr (P, 3), FP64 numpy.  wi (P, N, 3), O (P, N), Lind (P, N, 3),
-    env (6, E, E, 3)."""
+    env (6, E, E, 3); wgt (P, N) optional per-sample weights (see _weights)."""
     n, wo, albedo, rough, wi, O, Lind, env = (np.asarray(a, np.float64) for a in
                                                 (n, wo, albedo, rough, wi, O, Lind, env))
     N, E = wi.shape[1], env.shape[1]
+    # 1 / (N pdf): 2 pi / N for the uniform hemisphere, else the caller's
+    # per-sample weights (0 for a sample below the horizon)
+    w = 2.0 * np.pi / N if wgt is None else np.asarray(wgt, np.float64)[..., None]
     fs, ndl = _brdf_spec(n, wo, wi, rough, np)
     f, row, col = cube_texel(wi, E, texel_dtype)
     Ldir = env[f, row, col]                                      # (P, N, 3)
     Li = (1.0 - O)[..., None] * Ldir + Lind
     brdf = albedo[:, None, :] / np.pi + fs[..., None]
-    return 2.0 * np.pi / N * (brdf * Li * ndl[..., None]).sum(1)
+    return (w * brdf * Li * ndl[..., None]).sum(1)
 
 
-def shade_grad(n, wo, albedo, rough, wi, O, Lind, env, g_c, texel_dtype=np.float64):
+def shade_grad(n, wo, albedo, rough, wi, O, Lind, env, g_c, texel_dtype=np.float64, wgt=None):
     """FP64 autograd gradients of sum(g_c * c_pbr) with respect to albedo,
-    roughness, the cubemap, O and L_ind."""
+    roughness, the cubemap, O and L_ind (optional per-sample weights wgt)."""
     t = lambda a: torch.tensor(np.asarray(a, np.float64))
     n_t, wo_t, wi_t = t(n), t(wo), t(wi)
     albedo_t, rough_t, O_t, Lind_t, env_t = (t(a).requires_grad_(True) for a in (albedo, rough, O, Lind, env))
@@ -147,7 +154,8 @@ def shade_grad(n, wo, albedo, rough, wi, O, Lind, env, g_c, texel_dtype=np.float
     Ldir = env_t[torch.tensor(f), torch.tensor(row), torch.tensor(col)]
     Li = (1.0 - O_t)[..., None] * Ldir + Lind_t
     brdf = albedo_t[:, None, :] / np.pi + fs[..., None]
-    c = 2.0 * np.pi / N * (brdf * Li * ndl[..., None]).sum(1)
+    w = 2.0 * np.pi / N if wgt is None else t(wgt)[..., None]
+    c = (w * brdf * Li * ndl[..., None]).sum(1)
     L = (t(g_c) * c).sum()
     g = torch.autograd.grad(L, [albedo_t, rough_t, env_t, O_t, Lind_t])
     return dict(zip(("albedo", "rough", "env", "O", "Lind"), (x.numpy() for x in g)))

@@ -107,3 +107,92 @@ def test_trace_oracle_normal_channels():
     np.testing.assert_allclose(r["F"][1, 4:], [0, 0, -0.6], atol=1e-15)
     rep = oracle.replay(S, ro, rd, np.array([[0], [0]], np.int32), np.array([1, 1], np.int32), with_normal=True)
     np.testing.assert_allclose(rep["F"], r["F"], rtol=1e-15)
+
+
+def _quad_cos_integral(env, nrm, m=24):
+    """int L(w) max(w . nrm, 0) dw for the piecewise-constant cubemap, by an
+    m x m midpoint rule inside every texel in the face coordinates
+    (dw = ds dt / (1 + s^2 + t^2)^{3/2}); independent of the sampler."""
+    E = env.shape[1]
+    c = (np.arange(E * m) + 0.5) / (E * m) * 2.0 - 1.0
+    t, s = np.meshgrid(c, c, indexing="ij")
+    jac = (2.0 / (E * m)) ** 2 / (1.0 + s * s + t * t) ** 1.5
+    tot = 0.0
+    for f in range(6):
+        d = rl.face_point(f, s, t)
+        d = d / np.linalg.norm(d, axis=-1, keepdims=True)
+        cos = np.maximum(d @ nrm, 0.0)
+        L = env[f].mean(-1).repeat(m, 0).repeat(m, 1)
+        tot += np.sum(L * cos * jac)
+    return tot
+
+
+def test_env_sampling_one_hot_sky():
+    """A sky lit in one texel: every sample lands in that texel, with
+    density E^2/4 (1 + s^2 + t^2)^{3/2} (probability 1 for the texel)."""
+    E, P, N = 4, 2, 500
+    env = np.zeros((6, E, E, 3))
+    env[2, 1, 3] = [1.0, 2.0, 3.0]                              # face +y, row 1, col 3
+    cdf = rl.env_cdf(env)
+    assert np.all(np.diff(cdf) >= 0)
+    g = np.random.default_rng(81)
+    u = g.random((P, N, 3))
+    n = np.array([[0, 1.0, 0], [0, -1.0, 0]])
+    ro, rd, w = rl.env_sample(np.zeros((P, 3)), n, u, cdf.astype(np.float32), E)
+    f, r, c = osh.cube_texel(rd.reshape(-1, 3), E)
+    assert np.all(f == 2) and np.all(r == 1) and np.all(c == 3)
+    s = (3 + u[..., 1]) * 2.0 / E - 1.0
+    t = (1 + u[..., 2]) * 2.0 / E - 1.0
+    pdf = E * E / 4.0 * (1 + s * s + t * t) ** 1.5
+    np.testing.assert_allclose(w[0], 1.0 / (N * pdf[0]), rtol=1e-12)
+    np.testing.assert_array_equal(w[1], 0.0)                    # the lit texel is below this horizon
+    np.testing.assert_allclose(ro, np.broadcast_to((1e-3 * n)[:, None, :], ro.shape))
+
+
+def test_env_sampling_frequencies_and_unbiased_estimate():
+    """Texels are drawn with the CDF's probabilities, and the weighted sum
+    sum_i w_i L(w_i) (w_i . n) estimates the integral of L cos over the
+    hemisphere, computed independently by quadrature (within 5 sigma)."""
+    E = 2
+    g = np.random.default_rng(82)
+    env = g.uniform(0.0, 1.0, (6, E, E, 3)) ** 3 * 10         # contrasty sky
+    cdf = rl.env_cdf(env)
+    _, dw = rl.texel_dirs(E)
+    np.testing.assert_allclose(cdf[-1], np.sum(env.mean(-1) * dw[None]), rtol=1e-12)
+    p = np.diff(np.concatenate([[0.0], cdf])) / cdf[-1]
+    N = 400_000
+    nrm = np.array([0.3, 0.5, 0.81])
+    nrm /= np.linalg.norm(nrm)
+    u = g.random((1, N, 3))
+    _, rd, w = rl.env_sample(np.zeros((1, 3)), nrm[None], u, cdf.astype(np.float32), E)
+    f, r, c = osh.cube_texel(rd[0], E)
+    cnt = np.bincount((f * E + r) * E + c, minlength=6 * E * E) / N
+    assert np.all(np.abs(cnt - p) <= 5 * np.sqrt(p * (1 - p) / N) + 1e-12)
+    L = env[f, r, c].mean(-1)
+    terms = N * w[0] * L * np.maximum(rd[0] @ nrm, 0.0)        # one-sample estimates
+    est, sig = terms.mean(), terms.std() / np.sqrt(N)
+    ref = _quad_cos_integral(env, nrm)
+    assert abs(est - ref) < 5 * sig, (est, ref, sig)
+    # a uniform sky: the estimate of the cosine integral is pi
+    one = np.ones((6, 8, 8, 3))
+    _, rd1, w1 = rl.env_sample(np.zeros((1, 3)), nrm[None], u[:, :100_000], rl.env_cdf(one).astype(np.float32), 8)
+    t1 = 100_000 * w1[0] * np.maximum(rd1[0] @ nrm, 0.0)
+    assert abs(t1.mean() - math.pi) < 5 * t1.std() / np.sqrt(t1.size)
+
+
+def test_weighted_shading_reduces_to_stratified():
+    """Eq. 15 with every weight 2 pi / N is the stratified estimator."""
+    g = np.random.default_rng(83)
+    P, N, E = 3, 8, 4
+    n = np.tile([0, 0, 1.0], (P, 1))
+    wo = osh.stratified_dirs(n, g.random((P, 1, 2)), 1, 1)[:, 0]
+    a, r = g.random((P, 3)), g.uniform(0.1, 0.9, P)
+    wi = osh.stratified_dirs(n, g.random((P, N, 2)), 2, 4)
+    O, L, env = g.random((P, N)), g.random((P, N, 3)), g.random((6, E, E, 3))
+    wgt = np.full((P, N), 2 * math.pi / N)
+    np.testing.assert_allclose(osh.shade(n, wo, a, r, wi, O, L, env, wgt=wgt),
+                               osh.shade(n, wo, a, r, wi, O, L, env), rtol=1e-13)
+    g1 = osh.shade_grad(n, wo, a, r, wi, O, L, env, np.ones((P, 3)), wgt=wgt)
+    g2 = osh.shade_grad(n, wo, a, r, wi, O, L, env, np.ones((P, 3)))
+    for k in g1:
+        np.testing.assert_allclose(g1[k], g2[k], rtol=1e-12, atol=1e-15)
