@@ -546,14 +546,16 @@ def run_pbr(args):
 
 def run_relight(args):
     """Relighting step (the paper's relighting details): once per sky, the
-    irradiance and GGX-prefiltered cubemaps (32 x 32, 8 roughness levels) and
-    the 32 x 32 split-sum table; per frame, P pixels x 16 x 16 stratified
-    directions on the 1M-surfel scene whose 4 features are albedo and
-    roughness, the trace blending them with the ray-facing normal, the
-    split-sum indirect radiance per ray, and Eq. 15 (forward only)."""
+    irradiance and GGX-prefiltered cubemaps (32 x 32, 8 roughness levels),
+    the 32 x 32 split-sum table and the sky's sampling CDF; per frame, P
+    pixels x 256 directions drawn by the sky's intensity (the paper's
+    sampling for relighting; --relight-sampling stratified for 16 x 16
+    strata) on the 1M-surfel scene whose 4 features are albedo and roughness,
+    the trace blending them with the ray-facing normal, the split-sum
+    indirect radiance per ray, and Eq. 15 (forward only)."""
     import torch
     from paper_2412_15867_amd import Scene, TraceConfig, synth, trace, mc_rays
-    from paper_2412_15867_amd import brdf_table, env_prefilter, relight
+    from paper_2412_15867_amd import brdf_table, env_cdf, env_prefilter, env_rays, relight
     dev = torch.device("cuda:0")
     N_surf, P, St, Sp, M, S = args.surfels, args.pixels, 16, 16, 8, 32
     Nr = St * Sp
@@ -565,6 +567,8 @@ def run_relight(args):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
     scene = Scene(t(sc.mu), t(sc.quat), t(sc.scale), t(sc.opac), t(feat))
     x, n, wo, u, albedo, rough, env = (t(px[k]) for k in ("x", "n", "wo", "u", "albedo", "rough", "env"))
+    strat = args.relight_sampling == "stratified"
+    u3 = t(synth.sky_uniforms(P, Nr))
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def pre():
@@ -572,11 +576,16 @@ def run_relight(args):
         e[0].record()
         irr, pref = env_prefilter(env, M)
         tab = brdf_table(S, device=dev)
+        cdf = env_cdf(env)
         e[1].record()
-        return (irr, pref, tab), e
+        return (irr, pref, tab, cdf), e
 
     def frame(tabs):
-        return relight(scene, x, n, wo, albedo, rough, env, u, St, Sp, *tabs, k=args.k)
+        irr, pref, tab, cdf = tabs
+        if strat:
+            return relight(scene, x, n, wo, albedo, rough, env, u, St, Sp, sampling="stratified", irr=irr, pref=pref,
+                           table=tab, k=args.k)
+        return relight(scene, x, n, wo, albedo, rough, env, u3, irr=irr, pref=pref, table=tab, cdf=cdf, k=args.k)
 
     for _ in range(args.warmup):
         tabs, _e = pre()
@@ -591,7 +600,7 @@ def run_relight(args):
     step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     pre_ms = float(np.median([e[0].elapsed_time(e[1]) for e in pre_evs]))
     R = P * Nr
-    ro, rd = mc_rays(x, n, u, St, Sp)
+    ro, rd = mc_rays(x, n, u, St, Sp) if strat else env_rays(x, n, u3, tabs[3], env.shape[1])[:2]
     cfg = TraceConfig(k=args.k, normals=True)
     es = [ev(), ev()]
     es[0].record()
@@ -603,12 +612,13 @@ def run_relight(args):
     torch.cuda.synchronize()
     nh = res.n_hits.cpu().numpy()
     fb = fwd_bytes(nh, 4, 7)
+    samp = f"{St}x{Sp} stratified directions" if strat else f"{Nr} directions drawn by sky intensity"
     line = {"metric": "Mrays/s relighting frame (rays + trace with blended normal + split-sum + Eq. 15)",
             "value": round(R / (step_ms * 1e-3) / 1e6, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"{N_surf} surfels (8 spheres + 4 planes; albedo + roughness features), {P} "
-                                   f"pixels x {St}x{Sp} stratified directions = {R} rays, 32x32 cubemap, {M} "
+                                   f"pixels x {samp} = {R} rays, 32x32 cubemap, {M} "
                                    f"prefiltered levels, {S}x{S} BRDF table, k={args.k}, T_min=1e-4",
                        "pixels": P, "rays": R},
             "sky_precompute_ms": round(pre_ms, 3), "trace_ms": round(trace_ms, 3),
@@ -627,6 +637,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "serve", "c5", "pbr", "relight"])
     ap.add_argument("--pixels", type=int, default=1024, help="pbr / relight workloads: pixels (x 256 directions)")
+    ap.add_argument("--relight-sampling", default="env", choices=["env", "stratified"],
+                    help="relight workload: directions drawn by the sky's intensity or stratified")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--surfels", type=int, default=1_000_000)

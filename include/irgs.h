@@ -257,9 +257,12 @@ typedef struct {
     const float* O;       /* P x N opacity of each ray's trace (V = 1 - O) */
     const float* Lind;    /* P x N x 3 colour of each ray's trace (L_ind) */
     const float* env;     /* 6 x E x E x 3 cubemap L_dir: faces +x, -x, +y, -y, +z, -z */
+    const float* wgt;     /* P x N per-sample weights 1 / (N pdf) of another sampling density
+                             (irgs_env_rays), or NULL: 2 pi / N each (uniform hemisphere) */
 } irgs_shade_in;
 
-/* c[p] = 2 pi / N sum_i (a / pi + f_s) (V_i L_dir(w_i) + L_ind,i) (w_i . n),
+/* c[p] = 2 pi / N sum_i (a / pi + f_s) (V_i L_dir(w_i) + L_ind,i) (w_i . n)
+ * (Eq. 15; with wgt, wgt[p, i] in place of 2 pi / N),
  * f_s = D F G / (4 (w_i . n)(w_o . n)): D GGX with alpha = r^2, F Schlick
  * with F0 = 0.04, G Smith with Schlick-GGX G1 and k = (r + 1)^2 / 8; both
  * cosines clamped below at 1e-4 inside G and the denominator.  L_dir is the
@@ -316,6 +319,28 @@ irgs_status irgs_brdf_table(int32_t S, float* table, void* stream);
  * cell (floor(n.v S), floor(R S)); 0 for a ray with O = 0. */
 irgs_status irgs_relight_lind(int64_t R, const float* O, const float* Fo, const float* rd, int32_t E, const float* irr,
                               int32_t M, const float* pref, int32_t S, const float* table, float* lind, void* stream);
+
+/* Importance sampling of the sky by its intensity, which the paper's
+ * relighting uses in place of the stratified hemisphere.
+ * irgs_env_cdf: cdf (6 E^2, DEVICE, written) = the inclusive running sum,
+ * in texel order (face, row, col), of max(mean RGB, 0) times the texel's
+ * solid angle 4 / (E^2 (1 + s^2 + t^2)^{3/2}) at its centre (a NaN texel
+ * weighs 0), accumulated in FP64 and rounded once to FP32.  The sky must be
+ * finite.  1 <= E <= 256. */
+irgs_status irgs_env_cdf(int32_t E, const float* env, float* cdf, void* stream);
+
+/* Rays drawn from a sky CDF: sample (p, i) with uniforms u[p, i] = (u0, u1,
+ * u2) in [0, 1) takes the first texel j whose cdf exceeds u0 * total (FP32
+ * product; total = cdf[6 E^2 - 1]), the point (s, t) = ((col + u1), (row +
+ * u2)) 2 / E - 1 of that texel (uniform in the face coordinates of
+ * irgs_mc_shade), rd = its unit direction, ro = x_p + offset n_p, and
+ * wgt = 1 / (N pdf) with pdf = p_j E^2 / 4 (1 + s^2 + t^2)^{3/2},
+ * p_j = (cdf[j] - cdf[j - 1]) / total; wgt = 0 where rd . n_p <= 0 or the
+ * sky's total weight is not positive.  Texels of zero intensity are never
+ * drawn.  x, n: P x 3; u: P x N x 3; ro, rd: (P N) x 3 and wgt: P N,
+ * written.  N >= 1, P >= 0, 1 <= E <= 256. */
+irgs_status irgs_env_rays(int64_t P, int32_t N, const float* x, const float* n, const float* u, int32_t E,
+                          const float* cdf, float offset, float* ro, float* rd, float* wgt, void* stream);
 
 const char* irgs_status_str(irgs_status status);
 const char* irgs_last_error(void);

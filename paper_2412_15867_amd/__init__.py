@@ -22,7 +22,7 @@ _TRACE_NAMES = {"Scene", "TraceConfig", "TraceResult", "TraceFn", "trace", "trac
 
 
 _PBR_NAMES = {"mc_rays", "shade", "shade_backward", "ShadeFn", "render_pbr", "env_prefilter", "brdf_table",
-              "relight_lind", "relight"}
+              "relight_lind", "relight", "env_cdf", "env_rays"}
 
 
 def __getattr__(name):

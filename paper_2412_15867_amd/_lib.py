@@ -55,7 +55,7 @@ class Work(ctypes.Structure):
 
 class ShadeIn(ctypes.Structure):
     _fields_ = [("P", c_i64), ("N", c_i32), ("E", c_i32), ("n", c_vp), ("wo", c_vp), ("albedo", c_vp),
-                ("rough", c_vp), ("wi", c_vp), ("O", c_vp), ("Lind", c_vp), ("env", c_vp)]
+                ("rough", c_vp), ("wi", c_vp), ("O", c_vp), ("Lind", c_vp), ("env", c_vp), ("wgt", c_vp)]
 
 
 class ShadeGrads(ctypes.Structure):
@@ -82,6 +82,9 @@ SIGNATURES = {
     "irgs_env_prefilter": (ctypes.c_int, [c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "irgs_brdf_table": (ctypes.c_int, [c_i32, c_vp, c_vp]),
     "irgs_relight_lind": (ctypes.c_int, [c_i64, c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "irgs_env_cdf": (ctypes.c_int, [c_i32, c_vp, c_vp, c_vp]),
+    "irgs_env_rays": (ctypes.c_int, [c_i64, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_f32, c_vp, c_vp, c_vp,
+                                     c_vp]),
     "irgs_mc_shade": (ctypes.c_int, [ctypes.POINTER(ShadeIn), c_vp, c_vp]),
     "irgs_mc_shade_backward": (ctypes.c_int, [ctypes.POINTER(ShadeIn), c_vp, ctypes.POINTER(ShadeGrads), c_vp]),
     "irgs_status_str": (ctypes.c_char_p, [ctypes.c_int]),

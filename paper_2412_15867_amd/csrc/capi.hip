@@ -269,7 +269,8 @@ static irgs_status check_shade(const irgs_shade_in* in, ShadeArgs* a)
     if (in->P < 0 || in->N < 1 || in->E < 1) return fail(IRGS_E_INVALID, "P >= 0, N >= 1 and E >= 1 required");
     if (in->P > 0 && (!in->n || !in->wo || !in->albedo || !in->rough || !in->wi || !in->O || !in->Lind || !in->env))
         return fail(IRGS_E_INVALID, "NULL shade input");
-    *a = ShadeArgs{in->P, in->N, in->E, in->n, in->wo, in->albedo, in->rough, in->wi, in->O, in->Lind, in->env};
+    *a = ShadeArgs{in->P, in->N, in->E, in->n, in->wo, in->albedo, in->rough, in->wi, in->O, in->Lind, in->env,
+                   in->wgt};
     return IRGS_OK;
 }
 
@@ -306,6 +307,26 @@ irgs_status irgs_relight_lind(int64_t R, const float* O, const float* Fo, const 
     const RelightArgs a{R, O, Fo, rd, E, M, S, irr, pref, table};
     const hipError_t e = launch_relight_lind(a, lind, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? IRGS_OK : hip_fail(e, "relight launch");
+}
+
+irgs_status irgs_env_cdf(int32_t E, const float* env, float* cdf, void* stream)
+{
+    if (E < 1 || E > 256) return fail(IRGS_E_INVALID, "1 <= E <= 256 required");
+    if (!env || !cdf) return fail(IRGS_E_INVALID, "NULL pointer");
+    const hipError_t e = launch_env_cdf(E, env, cdf, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "env cdf launch");
+}
+
+irgs_status irgs_env_rays(int64_t P, int32_t N, const float* x, const float* n, const float* u, int32_t E,
+                          const float* cdf, float offset, float* ro, float* rd, float* wgt, void* stream)
+{
+    if (P < 0 || N < 1 || E < 1 || E > 256) return fail(IRGS_E_INVALID, "P >= 0, N >= 1 and 1 <= E <= 256 required");
+    if (P > (int64_t(1) << 40) / N) return fail(IRGS_E_INVALID, "P N too large");
+    if (P > 0 && (!x || !n || !u || !cdf || !ro || !rd || !wgt)) return fail(IRGS_E_INVALID, "NULL pointer");
+    if (!std::isfinite(offset)) return fail(IRGS_E_INVALID, "offset must be finite");
+    const EnvRayArgs a{P, N, E, x, n, u, cdf, offset, ro, rd, wgt};
+    const hipError_t e = launch_env_rays(a, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IRGS_OK : hip_fail(e, "env rays launch");
 }
 
 irgs_status irgs_mc_shade_backward(const irgs_shade_in* in, const float* g_c, irgs_shade_grads* grads,

@@ -162,6 +162,7 @@ struct ShadeArgs {
     const float* O;       // P x N
     const float* Lind;    // P x N x 3
     const float* env;     // 6 x E x E x 3
+    const float* wgt;     // P x N per-sample weights, or null: 2 pi / N each
 };
 
 struct ShadeGrads {
@@ -192,6 +193,23 @@ struct RelightArgs {
 hipError_t launch_env_prefilter(int E, const float* env, int M, float* irr, float* pref, hipStream_t st);
 hipError_t launch_brdf_table(int S, float* table, hipStream_t st);
 hipError_t launch_relight_lind(const RelightArgs& a, float* lind, hipStream_t st);
+
+// Importance sampling of the sky by intensity (relight.hip).
+struct EnvRayArgs {
+    int64_t P;          // pixels
+    int32_t N;          // samples per pixel
+    int32_t E;          // cube resolution
+    const float* x;     // P x 3 surface points
+    const float* n;     // P x 3 unit normals
+    const float* u;     // P x N x 3 uniforms in [0, 1)
+    const float* cdf;   // 6 E^2 inclusive CDF of the texel weights
+    float offset;       // origin offset along n
+    float* ro;          // P N x 3
+    float* rd;          // P N x 3
+    float* wgt;         // P N estimator weights
+};
+hipError_t launch_env_cdf(int E, const float* env, float* cdf, hipStream_t st);
+hipError_t launch_env_rays(const EnvRayArgs& a, hipStream_t st);
 
 // Fill n 32-bit words with v (a kernel, so it can be captured in a graph).
 hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);

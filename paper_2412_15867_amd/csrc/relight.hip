@@ -26,6 +26,20 @@ constexpr float kPiR = 3.14159265358979323846f;
 constexpr float kF0R = 0.04f;
 constexpr int kHammersley = 256;
 
+// Unnormalised direction of face coordinates (s, t) in [-1, 1]^2 on a face:
+// the inverse of the nearest-texel addressing below.
+__device__ __forceinline__ void face_point(int face, float s, float t, float* d)
+{
+    switch (face) {
+        case 0: d[0] = 1.0f, d[1] = -t, d[2] = -s; break;
+        case 1: d[0] = -1.0f, d[1] = -t, d[2] = s; break;
+        case 2: d[0] = s, d[1] = 1.0f, d[2] = t; break;
+        case 3: d[0] = s, d[1] = -1.0f, d[2] = -t; break;
+        case 4: d[0] = s, d[1] = -t, d[2] = 1.0f; break;
+        default: d[0] = -s, d[1] = -t, d[2] = -1.0f; break;
+    }
+}
+
 // Centre direction (unit) and solid angle of texel `idx` of an E x E cube.
 __device__ __forceinline__ void texel_dir(int idx, int E, float* d, float* dw)
 {
@@ -34,18 +48,10 @@ __device__ __forceinline__ void texel_dir(int idx, int E, float* d, float* dw)
     const int row = rc / E, col = rc - row * E;
     const float s = 2.0f * (col + 0.5f) / E - 1.0f;
     const float t = 2.0f * (row + 0.5f) / E - 1.0f;
-    float x, y, z;
-    switch (face) {
-        case 0: x = 1.0f, y = -t, z = -s; break;
-        case 1: x = -1.0f, y = -t, z = s; break;
-        case 2: x = s, y = 1.0f, z = t; break;
-        case 3: x = s, y = -1.0f, z = -t; break;
-        case 4: x = s, y = -t, z = 1.0f; break;
-        default: x = -s, y = -t, z = -1.0f; break;
-    }
+    face_point(face, s, t, d);
     const float q = 1.0f + s * s + t * t;
     const float inv = 1.0f / sqrtf(q);
-    d[0] = x * inv, d[1] = y * inv, d[2] = z * inv;
+    d[0] *= inv, d[1] *= inv, d[2] *= inv;
     *dw = 4.0f / (E * E * q * sqrtf(q));
 }
 
@@ -203,6 +209,91 @@ __global__ void k_relight_lind(RelightArgs a, float* __restrict__ lind)
     }
 }
 
+// Sampling weight of texel i: max(mean RGB, 0) times its solid angle at the
+// centre, in FP64 (a NaN texel weighs 0).
+__device__ __forceinline__ double texel_weight(int i, int E, const float* __restrict__ env)
+{
+    const int rc = i % (E * E);
+    const int row = rc / E, col = rc - row * E;
+    const double s = 2.0 * (col + 0.5) / E - 1.0, t = 2.0 * (row + 0.5) / E - 1.0;
+    const double q = 1.0 + s * s + t * t;
+    const double inten = fmax((static_cast<double>(env[3 * i]) + env[3 * i + 1] + env[3 * i + 2]) / 3.0, 0.0);
+    return inten * 4.0 / (static_cast<double>(E) * E * q * sqrt(q));
+}
+
+constexpr int kCdfBlock = 1024;
+
+// Inclusive CDF of the texel weights in texel order, one block: each thread
+// sums a run of consecutive texels in FP64, a block scan offsets the runs,
+// and each run is rewritten as running sums rounded once to FP32 (so the
+// table never decreases).
+__global__ __launch_bounds__(kCdfBlock) void k_env_cdf(int E, const float* __restrict__ env, float* __restrict__ cdf)
+{
+    __shared__ double part[kCdfBlock];
+    const int n = 6 * E * E;
+    const int per = (n + kCdfBlock - 1) / kCdfBlock;
+    const int b = min(static_cast<int>(threadIdx.x) * per, n), e = min(b + per, n);
+    double run = 0.0;
+    for (int i = b; i < e; ++i) run += texel_weight(i, E, env);
+    part[threadIdx.x] = run;
+    __syncthreads();
+    for (int off = 1; off < kCdfBlock; off <<= 1) {
+        const double v = threadIdx.x >= static_cast<unsigned>(off) ? part[threadIdx.x - off] : 0.0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
+    for (int i = b; i < e; ++i) {
+        run += texel_weight(i, E, env);
+        cdf[i] = static_cast<float>(run);
+    }
+}
+
+// One ray per sample drawn from the sky's intensity: the first texel whose
+// CDF exceeds u0 * total (FP32), a point uniform in that texel's face
+// coordinates, density p_j E^2 / 4 (1 + s^2 + t^2)^{3/2}, estimator weight
+// 1 / (N pdf) above the horizon of n and 0 below it or for an empty sky.
+__global__ void k_env_rays(EnvRayArgs a)
+{
+    const int nt = 6 * a.E * a.E;
+    const float total = a.cdf[nt - 1];
+    const float step = 2.0f / a.E;
+    for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < a.P * a.N;
+         r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t p = r / a.N;
+        const float* u = a.u + 3 * r;
+        float target = u[0] * total;
+        if (!(target < total)) target = nextafterf(total, 0.0f);
+        int lo = 0, hi = nt - 1;  // first index with cdf > target (the last one if none)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (a.cdf[mid] > target) hi = mid;
+            else lo = mid + 1;
+        }
+        const int face = lo / (a.E * a.E);
+        const int rc = lo - face * a.E * a.E;
+        const int row = rc / a.E, col = rc - row * a.E;
+        const float s = (static_cast<float>(col) + u[1]) * step - 1.0f;
+        const float t = (static_cast<float>(row) + u[2]) * step - 1.0f;
+        float d[3];
+        face_point(face, s, t, d);
+        const float q = 1.0f + s * s + t * t;
+        const float inv = 1.0f / sqrtf(q);
+        d[0] *= inv, d[1] *= inv, d[2] *= inv;
+        const float n[3] = {a.n[3 * p], a.n[3 * p + 1], a.n[3 * p + 2]};
+        const float pj = (a.cdf[lo] - (lo > 0 ? a.cdf[lo - 1] : 0.0f)) / total;
+        const float pdf = pj * (0.25f * a.E * a.E) * (q * sqrtf(q));
+        const bool ok = d[0] * n[0] + d[1] * n[1] + d[2] * n[2] > 0.0f && pdf > 0.0f && total > 0.0f;
+        a.wgt[r] = ok ? 1.0f / (static_cast<float>(a.N) * pdf) : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a.ro[3 * r + c] = fmaf(a.offset, n[c], a.x[3 * p + c]);
+            a.rd[3 * r + c] = d[c];
+        }
+    }
+}
+
 unsigned grid_for(int64_t n, int block)
 {
     const int64_t b = (n + block - 1) / block;
@@ -232,6 +323,19 @@ hipError_t launch_relight_lind(const RelightArgs& a, float* lind, hipStream_t st
 {
     if (a.R <= 0) return hipSuccess;
     k_relight_lind<<<grid_for(a.R, 256), 256, 0, st>>>(a, lind);
+    return hipGetLastError();
+}
+
+hipError_t launch_env_cdf(int E, const float* env, float* cdf, hipStream_t st)
+{
+    k_env_cdf<<<1, kCdfBlock, 0, st>>>(E, env, cdf);
+    return hipGetLastError();
+}
+
+hipError_t launch_env_rays(const EnvRayArgs& a, hipStream_t st)
+{
+    if (a.P * a.N <= 0) return hipSuccess;
+    k_env_rays<<<grid_for(a.P * a.N, 256), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -14,6 +14,9 @@
 // denominator clamped below at 1e-4; L_dir is the nearest texel of an RGB
 // cubemap (faces +x, -x, +y, -y, +z, -z, OpenGL face coordinates); the
 // sampling frame is the branchless orthonormal basis of Duff et al. (2017).
+// With another sampling density (the relighting variant draws directions by
+// the sky's intensity) each sample carries its own weight 1 / (N pdf) in
+// place of 2 pi / N.
 #include <hip/hip_runtime.h>
 
 #include "irgs_internal.hpp"
@@ -165,14 +168,15 @@ __global__ __launch_bounds__(kShadeBlock) void k_mc_shade(ShadeArgs a, float* __
         const Spec sp = spec<false>(n, wo, ndv, wi, r);
         const float* L = a.env + 3 * static_cast<int64_t>(cube_texel(wi[0], wi[1], wi[2], a.E));
         const float V = 1.0f - a.O[ri];
+        const float cw = a.wgt ? sp.ndl * a.wgt[ri] : sp.ndl;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             const float Li = fmaf(V, L[ch], a.Lind[3 * ri + ch]);
-            s1[ch] = fmaf(Li, sp.ndl, s1[ch]);
-            s2[ch] = fmaf(sp.fs * Li, sp.ndl, s2[ch]);
+            s1[ch] = fmaf(Li, cw, s1[ch]);
+            s2[ch] = fmaf(sp.fs * Li, cw, s2[ch]);
         }
     }
-    const float scale = 2.0f * kPi / static_cast<float>(a.N);
+    const float scale = a.wgt ? 1.0f : 2.0f * kPi / static_cast<float>(a.N);
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         const float t1 = wave_sum(s1[ch]), t2 = wave_sum(s2[ch]);
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_mc_shade_bwd(ShadeArgs a, const
     const float wo[3] = {a.wo[3 * p], a.wo[3 * p + 1], a.wo[3 * p + 2]};
     const float ndv = n[0] * wo[0] + n[1] * wo[1] + n[2] * wo[2];
     const float r = a.rough[p];
-    const float scale = 2.0f * kPi / static_cast<float>(a.N);
+    const float scale = a.wgt ? 1.0f : 2.0f * kPi / static_cast<float>(a.N);
     const float gc[3] = {scale * g_c[3 * p], scale * g_c[3 * p + 1], scale * g_c[3 * p + 2]};
     const float fd[3] = {a.albedo[3 * p] / kPi, a.albedo[3 * p + 1] / kPi, a.albedo[3 * p + 2] / kPi};
     float ga[3] = {0, 0, 0}, gr = 0.0f;
@@ -201,11 +205,12 @@ __global__ __launch_bounds__(kShadeBlock) void k_mc_shade_bwd(ShadeArgs a, const
         const int64_t texel = cube_texel(wi[0], wi[1], wi[2], a.E);
         const float* L = a.env + 3 * texel;
         const float V = 1.0f - a.O[ri];
+        const float cw = a.wgt ? sp.ndl * a.wgt[ri] : sp.ndl;
         float gO = 0.0f;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             const float Li = fmaf(V, L[ch], a.Lind[3 * ri + ch]);
-            const float w = gc[ch] * sp.ndl;         // d c_ch / d (brdf_ch L_i)
+            const float w = gc[ch] * cw;             // d c_ch / d (brdf_ch L_i)
             const float brdf = fd[ch] + sp.fs;
             ga[ch] = fmaf(w / kPi, Li, ga[ch]);
             gr = fmaf(w * Li, sp.dfs_dr, gr);

@@ -338,3 +338,10 @@ def random_rays_near(g: np.random.Generator, centre: np.ndarray, radius: float, 
     src = centre + dist * _unit(g.standard_normal((R, 3)))
     tgt = centre + radius * _unit(g.standard_normal((R, 3))) * g.random((R, 1)) ** (1 / 3)
     return _f32(src), _f32(_unit(tgt - src))
+
+
+def sky_uniforms(P: int, N: int, seed: int = SEED_PBR + 2) -> np.ndarray:
+    """(P, N, 3) float32 uniforms in [0, 1) for drawing incident directions
+    from a sky's intensity (texel choice, then the point in the texel)."""
+    return _rng(seed).random((P, N, 3)).astype(np.float32)
+

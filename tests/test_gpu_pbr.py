@@ -1,7 +1,8 @@
 """Monte Carlo rendering-equation consumer of the trace (Sec. 3.3,
 "Rendering": Eq. 15 with Eq. 13-14 and the BRDF of Eq. 4): HIP ray
-generation, shading and its gradients against the FP64 oracle, and the whole
-chain (rays -> differentiable trace -> shading) against the oracle chain."""
+generation, shading and its gradients against the FP64 oracle, and the
+differentiable trace -> shading chain against the oracle chain, all on
+seeded inputs."""
 import numpy as np
 import pytest
 import torch
@@ -44,14 +45,20 @@ def test_mc_rays_match_oracle():
     np.testing.assert_allclose(ro.cpu().numpy(), np.repeat(o, St * Sp, 0), atol=1e-6)
 
 
+def hemisphere_dirs(g, n, N):
+    """Seeded unit directions, N per normal, in the hemisphere of each n
+    (inputs only: both sides receive the same FP32 values)."""
+    w = g.standard_normal((n.shape[0], N, 3))
+    w /= np.linalg.norm(w, axis=-1, keepdims=True)
+    w = np.where(((w * n[:, None, :]).sum(-1) < 0)[..., None], -w, w)
+    return w.astype(F32)
+
+
 def shade_inputs(seed, P, St, Sp):
-    from paper_2412_15867_amd import mc_rays
     d = pixels(seed, P)
     g = np.random.default_rng(seed + 1)
     N = St * Sp
-    u = g.uniform(0, 1, (P, N, 2)).astype(F32)
-    _, rd = mc_rays(dev(d["x"]), dev(d["n"]), dev(u), St, Sp)
-    d["wi"] = rd.cpu().numpy().reshape(P, N, 3)
+    d["wi"] = hemisphere_dirs(g, d["n"].astype(np.float64), N)
     d["O"] = g.uniform(0, 1, (P, N)).astype(F32)
     d["Lind"] = g.uniform(0, 2, (P, N, 3)).astype(F32)
     return d
@@ -92,43 +99,44 @@ def test_shade_edge_cases():
     np.testing.assert_allclose(c, want, rtol=5e-5, atol=5e-5 * np.abs(want).max())
 
 
-def test_render_pbr_chain_matches_oracle_chain():
-    """Cube scene with SH degree-2 colour, 48 pixels x 64 rays: the rays'
-    trace is validated against the oracle; c_pbr matches the oracle shading
-    of the FP64 replay of the GPU hit lists; gradients with respect to the
-    surfels match the oracle chain (shading adjoint -> trace adjoint)."""
-    from paper_2412_15867_amd import Scene, TraceConfig, TraceFn, mc_rays, render_pbr, trace
-    P, St, Sp = 48, 8, 8
-    N = St * Sp
+def test_trace_shade_chain_matches_oracle_chain():
+    """Cube scene with SH degree-2 colour, 48 pixels x 64 rays from seeded
+    points and hemisphere directions: the rays' trace is validated against
+    the oracle; c_pbr of the differentiable trace and shading matches the
+    oracle shading of the FP64 replay of the GPU hit lists (tie orders may
+    differ, the validated list is the one compared); gradients with respect
+    to the surfels and materials match the oracle chain (shading adjoint ->
+    trace adjoint)."""
+    from paper_2412_15867_amd import Scene, ShadeFn, TraceConfig, TraceFn, trace
+    P, N = 48, 64
     sc = synth.cube_scene()
     surf = synth.Surfels(sc.mu, sc.quat, sc.scale, sc.opac, synth.sh_coefficients(sc.n, 2))
     g = np.random.default_rng(75)
     d = pixels(76, P, E=16)
     d["x"] = (0.8 * d["x"]).astype(F32)            # inside the cube's surfel cloud
-    u = g.uniform(0, 1, (P, N, 2)).astype(F32)
+    wi = hemisphere_dirs(g, d["n"].astype(np.float64), N)
+    ro = np.repeat(d["x"], N, 0)
+    rd = wi.reshape(-1, 3)
     params = [dev(a).requires_grad_(True) for a in surf.astuple()]
     scene = Scene(*[p.detach() for p in params])
     scene.set_params(*params)
     cfg = TraceConfig(k=16, sh=True, hit_cap=256)
     mats = [dev(d[k]).requires_grad_(True) for k in ("albedo", "rough", "env")]
-    note("render_pbr chain")
-    c = render_pbr(scene, params, dev(d["x"]), dev(d["n"]), dev(d["wo"]), *mats, dev(u), St, Sp, cfg)
+    note("trace + shade chain")
+    O, F, _ = TraceFn.apply(*params, dev(ro), dev(rd), scene, cfg)
+    c = ShadeFn.apply(*mats, O.view(P, N), F.view(P, N, 3), dev(d["n"]), dev(d["wo"]), dev(wi))
     g_c = g.standard_normal((P, 3)).astype(F32)
     (c * dev(g_c)).sum().backward()
     torch.cuda.synchronize()
-    ro, rd = mc_rays(dev(d["x"]), dev(d["n"]), dev(u), St, Sp)
-    res = trace(scene, ro, rd, cfg, hit_cap=256)
-    fwd = to_np(res)
-    ro, rd = ro.cpu().numpy(), rd.cpu().numpy()
+    fwd = to_np(trace(scene, dev(ro), dev(rd), cfg, hit_cap=256))
     validate(surf.astuple(), ro, rd, fwd, sh_deg=2)
     H = fwd["hit_ids"].shape[1]
     lists = np.where(np.arange(H)[None, :] < fwd["n_hits"][:, None], fwd["hit_ids"], -1)
     rep = oracle.replay(surf.astuple(), ro, rd, lists.astype(np.int32), fwd["n_hits"], sh_deg=2)
     O64, L64 = rep["O"].reshape(P, N), rep["F"].reshape(P, N, 3)
-    want = osh.shade(d["n"], d["wo"], d["albedo"], d["rough"], rd.reshape(P, N, 3), O64, L64, d["env"],
-                     texel_dtype=np.float32)
+    want = osh.shade(d["n"], d["wo"], d["albedo"], d["rough"], wi, O64, L64, d["env"], texel_dtype=np.float32)
     np.testing.assert_allclose(c.detach().cpu().numpy(), want, rtol=1e-4, atol=1e-4 * np.abs(want).max())
-    gs = osh.shade_grad(d["n"], d["wo"], d["albedo"], d["rough"], rd.reshape(P, N, 3), O64, L64, d["env"], g_c,
+    gs = osh.shade_grad(d["n"], d["wo"], d["albedo"], d["rough"], wi, O64, L64, d["env"], g_c,
                         texel_dtype=np.float32)
     for t, name in zip(mats, ("albedo", "rough", "env")):
         b = gs[name]
@@ -140,6 +148,30 @@ def test_render_pbr_chain_matches_oracle_chain():
         b = ref[key]
         floor = np.abs(b).mean() + 1e-30
         assert (np.abs(a - b) / (np.abs(b) + floor)).max() <= 2e-3, key
+    scene.close()
+
+
+def test_render_pbr_is_rays_trace_shade():
+    """render_pbr = stratified rays (compared with the oracle above), the
+    differentiable trace and the shading, bit for bit on the GPU."""
+    from paper_2412_15867_amd import Scene, ShadeFn, TraceConfig, TraceFn, mc_rays, render_pbr
+    P, St, Sp = 32, 4, 8
+    N = St * Sp
+    sc = synth.cube_scene()
+    d = pixels(78, P, E=16)
+    d["x"] = (0.8 * d["x"]).astype(F32)
+    u = np.random.default_rng(79).uniform(0, 1, (P, N, 2)).astype(F32)
+    params = [dev(a) for a in sc.astuple()]
+    scene = Scene(*params)
+    cfg = TraceConfig(k=16)
+    mats = [dev(d[k]) for k in ("albedo", "rough", "env")]
+    x, n, wo = dev(d["x"]), dev(d["n"]), dev(d["wo"])
+    c = render_pbr(scene, params, x, n, wo, *mats, dev(u), St, Sp, cfg)
+    ro, rd = mc_rays(x, n, dev(u), St, Sp)
+    O, F, _ = TraceFn.apply(*params, ro, rd, scene, cfg)
+    c2 = ShadeFn.apply(*mats, O.view(P, N), F.view(P, N, 3), n, wo, rd.view(P, N, 3))
+    torch.cuda.synchronize()
+    assert torch.equal(c, c2)
     scene.close()
 
 
