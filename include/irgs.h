@@ -106,6 +106,14 @@ typedef struct {
  * IRGS_FLAG_SH; k must be 16 or 32; not for the backward or the packed
  * launch. */
 #define IRGS_FLAG_NORMAL 8u
+/* scene build only: the binary tree under the 4-wide BVH comes from PLOC
+ * clustering (Meister and Bittner 2018: mutually nearest clusters by union
+ * surface area within 8 positions of the Morton order merge, iterated; the
+ * leaves are then renumbered depth first) instead of Karras' radix tree over
+ * the sorted Morton codes (the default).  Both trees give the same hits; the
+ * PLOC tree bounds them with less box area, so traversals test fewer
+ * surfels, at a slower build and refit. */
+#define IRGS_FLAG_PLOC_TREE 16u
 
 /* Outputs of a trace, caller-allocated (R = number of rays):
  *   opacity (R)      accumulated opacity O = sum T_i alpha_i (o_rt of Eq. 8;
@@ -183,9 +191,10 @@ irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, 
 irgs_status irgs_scene_set_params(irgs_scene scene, const irgs_surfels* params);
 
 /* Build: per-surfel records and support boxes, Morton codes, radix sort,
- * hierarchy, bottom-up boxes.  Allocates the scene's device buffers on
- * first use.  Uses params->alpha_min and params->support_sigma.  Reads the
- * tree depth back (synchronises `stream`). */
+ * hierarchy (radix tree, or PLOC with IRGS_FLAG_PLOC_TREE), bottom-up
+ * boxes, the 4-wide collapse.  Allocates the scene's device buffers on first
+ * use.  Uses params->alpha_min, support_sigma, leaf_size and that flag.
+ * Reads level sizes and the tree depth back (synchronises `stream`). */
 irgs_status irgs_scene_build(irgs_scene scene, const irgs_params* params, void* stream);
 
 /* Refit after the parameters changed in place: records, leaf boxes and

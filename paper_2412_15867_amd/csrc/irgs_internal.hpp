@@ -31,6 +31,7 @@ struct BuildArgs {
     int4* wsrc;             // per wide node and slot: (binary parent << 1 | side), -1 = empty
     int* wscratch;          // 2 * max(N - 1, 1) + 4 ints: frontiers and counters
     int leaf_size;          // surfels per cluster leaf (1..16)
+    bool ploc;              // binary tree by PLOC (else the Morton radix tree)
     int n_wide;             // out (host): wide nodes built; also the refit input
     int wide_depth;         // out (host): levels of the wide tree
 };

@@ -550,6 +550,189 @@ __global__ void k_wide_refit(int nw, const int4* __restrict__ wsrc, const BvhNod
 
 inline int blocks_for(int64_t n, int t) { return static_cast<int>((n + t - 1) / t); }
 
+// ---------------------------------------------------------------- PLOC
+// Parallel locally-ordered clustering (Meister and Bittner 2018): clusters
+// start as the leaves in Morton order; per iteration every cluster finds,
+// within kPlocRadius positions on either side, the cluster whose union with
+// it has the smallest surface area; mutually nearest pairs merge into a new
+// internal node (kept at the lower position), and the survivors are
+// compacted in order.  Ties go to the smaller position, so the pair with the
+// globally smallest (area, positions) is always mutual and every iteration
+// merges.  Node ids count down from n - 2: the last merge is the root, 0.
+constexpr int kPlocRadius = 8;
+constexpr int kPlocBlock = 256;
+
+__device__ __forceinline__ void box_union(const float* a, const float* b, float* u)
+{
+    const bool ea = box_empty(a), eb = box_empty(b);
+    for (int k = 0; k < 3; ++k) {
+        u[k] = ea ? b[k] : (eb ? a[k] : fminf(a[k], b[k]));
+        u[k + 3] = ea ? b[k + 3] : (eb ? a[k + 3] : fmaxf(a[k + 3], b[k + 3]));
+    }
+}
+
+// Merge cost: half the surface area of the union (0 for two empty boxes,
+// +inf for a non-finite area).  Symmetric bit for bit in its arguments.
+__device__ __forceinline__ float union_cost(const float* a, const float* b)
+{
+    if (box_empty(a) && box_empty(b)) return 0.0f;
+    float u[6];
+    box_union(a, b, u);
+    const float c = box_area(u);
+    return c == c ? c : __int_as_float(0x7f800000);
+}
+
+__global__ void k_ploc_init(int n, const float* __restrict__ leafbox, int* __restrict__ ref,
+                            float* __restrict__ box)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ref[i] = i | kLeafBit;
+    for (int k = 0; k < 6; ++k) box[6 * static_cast<int64_t>(i) + k] = leafbox[6 * static_cast<int64_t>(i) + k];
+}
+
+__global__ __launch_bounds__(kPlocBlock) void k_ploc_nn(int m, const float* __restrict__ box, int* __restrict__ nn)
+{
+    constexpr int kSpan = kPlocBlock + 2 * kPlocRadius;
+    __shared__ float sb[kSpan * 6];
+    const int base = blockIdx.x * kPlocBlock - kPlocRadius;
+    for (int t = threadIdx.x; t < kSpan * 6; t += kPlocBlock) {
+        const int g = base + t / 6;
+        sb[t] = (g >= 0 && g < m) ? box[6 * static_cast<int64_t>(base) + t] : 0.0f;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kPlocBlock + threadIdx.x;
+    if (i >= m) return;
+    const float* bi = sb + (threadIdx.x + kPlocRadius) * 6;
+    float best = 0.0f;
+    int bj = -1;
+    for (int d = -kPlocRadius; d <= kPlocRadius; ++d) {  // increasing positions: ties keep the smaller
+        const int j = i + d;
+        if (d == 0 || j < 0 || j >= m) continue;
+        const float c = union_cost(bi, bi + 6 * d);
+        if (bj < 0 || c < best) {
+            best = c;
+            bj = j;
+        }
+    }
+    nn[i] = bj;
+}
+
+// Mutual pairs merge (the lower position leads and keeps the new cluster in
+// place; pairs are disjoint, so no slot is read and written by two threads);
+// keep[i] flags the survivors and each block adds its count to *total.
+__global__ __launch_bounds__(kPlocBlock) void k_ploc_merge(int m, int* __restrict__ ref, float* __restrict__ box,
+                                                            const int* __restrict__ nn, BvhNode* __restrict__ nodes,
+                                                            uint32_t* __restrict__ keep,
+                                                            uint32_t* __restrict__ block_counts,
+                                                            int* __restrict__ node_counter, int top,
+                                                            uint32_t* __restrict__ total)
+{
+    __shared__ uint32_t wave_cnt[kPlocBlock / 64];
+    const int i = blockIdx.x * kPlocBlock + threadIdx.x;
+    bool kept = false;
+    if (i < m) {
+        const int j = nn[i];
+        const bool mutual = j >= 0 && nn[j] == i;
+        kept = !(mutual && j < i);
+        if (mutual && i < j) {
+            const int id = top - atomicAdd(node_counter, 1);
+            const int a = ref[i], b = ref[j];
+            const int ca = (a & kLeafBit) ? 1 : nodes[a].ch.w;
+            const int cb = (b & kLeafBit) ? 1 : nodes[b].ch.w;
+            nodes[id].ch = make_int4(a, b, -1, ca + cb);
+            if (!(a & kLeafBit)) nodes[a].ch.z = id;
+            if (!(b & kLeafBit)) nodes[b].ch.z = id;
+            float bi[6], bj[6], u[6];
+            for (int k = 0; k < 6; ++k) {
+                bi[k] = box[6 * static_cast<int64_t>(i) + k];
+                bj[k] = box[6 * static_cast<int64_t>(j) + k];
+            }
+            box_union(bi, bj, u);
+            for (int k = 0; k < 6; ++k) box[6 * static_cast<int64_t>(i) + k] = u[k];
+            ref[i] = id;
+        }
+        keep[i] = kept ? 1u : 0u;
+    }
+    const uint64_t bal = __ballot(kept);
+    if ((threadIdx.x & 63) == 0) wave_cnt[threadIdx.x >> 6] = static_cast<uint32_t>(__popcll(bal));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = 0;
+        for (int w = 0; w < kPlocBlock / 64; ++w) c += wave_cnt[w];
+        block_counts[blockIdx.x] = c;
+        atomicAdd(total, c);
+    }
+}
+
+// Survivors to their compacted positions, in order (block offsets from the
+// exclusive scan of the block counts, ranks inside the block by ballots).
+__global__ __launch_bounds__(kPlocBlock) void k_ploc_scatter(int m, const uint32_t* __restrict__ keep,
+                                                              const uint32_t* __restrict__ offsets,
+                                                              const int* __restrict__ ref_in,
+                                                              const float* __restrict__ box_in,
+                                                              int* __restrict__ ref_out, float* __restrict__ box_out)
+{
+    __shared__ uint32_t wave_cnt[kPlocBlock / 64];
+    const int i = blockIdx.x * kPlocBlock + threadIdx.x;
+    const bool kept = i < m && keep[i] != 0;
+    const uint64_t bal = __ballot(kept);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wave_cnt[wave] = static_cast<uint32_t>(__popcll(bal));
+    __syncthreads();
+    if (!kept) return;
+    uint32_t pos = offsets[blockIdx.x];
+    for (int w = 0; w < wave; ++w) pos += wave_cnt[w];
+    pos += static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
+    ref_out[pos] = ref_in[i];
+    for (int k = 0; k < 6; ++k) box_out[6 * static_cast<int64_t>(pos) + k] = box_in[6 * static_cast<int64_t>(i) + k];
+}
+
+__device__ __forceinline__ int ref_count(const BvhNode* nodes, int r)
+{
+    return (r & kLeafBit) ? 1 : nodes[r].ch.w;
+}
+
+// First depth-first leaf of every internal node: the leaves of the left
+// siblings of its ancestors (and of itself, when it is a right child).
+__global__ void k_tree_offsets(int nint, const BvhNode* __restrict__ nodes, int* __restrict__ first)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nint) return;
+    int off = 0, c = x, p = nodes[x].ch.z;
+    while (p >= 0) {
+        const int4 ch = nodes[p].ch;
+        if (ch.y == c) off += ref_count(nodes, ch.x);
+        c = p;
+        p = ch.z;
+    }
+    first[x] = off;
+}
+
+// Leaves renumbered in depth-first order: new order, leaf parents, leaf
+// references and the leaf range of every internal node.
+__global__ void k_tree_renumber(int nint, BvhNode* __restrict__ nodes, const int* __restrict__ first,
+                                const uint32_t* __restrict__ order_in, uint32_t* __restrict__ order_out,
+                                int* __restrict__ leaf_parent, int2* __restrict__ brange)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nint) return;
+    const int4 ch = nodes[x].ch;
+    const int f = first[x];
+    brange[x] = make_int2(f, ch.w);
+    if (ch.x & kLeafBit) {
+        order_out[f] = order_in[ch.x & ~kLeafBit];
+        leaf_parent[f] = x;
+        nodes[x].ch.x = f | kLeafBit;
+    }
+    if (ch.y & kLeafBit) {
+        const int pos = f + ref_count(nodes, ch.x);
+        order_out[pos] = order_in[ch.y & ~kLeafBit];
+        leaf_parent[pos] = x;
+        nodes[x].ch.y = pos | kLeafBit;
+    }
+}
+
 
 
 }  // namespace
@@ -563,12 +746,86 @@ hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st)
     return hipGetLastError();
 }
 
+// PLOC scratch: two cluster buffers (reference + box), neighbours, survivor
+// flags, first leaves, the renumbered order, block counts and two counters.
+static size_t ploc_scratch_bytes(int n)
+{
+    const size_t nb = static_cast<size_t>(blocks_for(n, kPlocBlock));
+    return static_cast<size_t>(n) * (2 * (sizeof(int) + 6 * sizeof(float)) + 4 * sizeof(int)) +
+           nb * sizeof(uint32_t) + 256;
+}
+
 hipError_t lbvh_sort_scratch_bytes(int n, size_t* bytes)
 {
     const int ntiles = blocks_for(n, kSortTile);
-    *bytes = static_cast<size_t>(n) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) +
-             static_cast<size_t>(ntiles) * kRadixBins * sizeof(uint32_t) + 64 * 6 * sizeof(float) + 256;
+    const size_t sort = static_cast<size_t>(n) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) +
+                        static_cast<size_t>(ntiles) * kRadixBins * sizeof(uint32_t) + 64 * 6 * sizeof(float) + 256;
+    const size_t ploc = ploc_scratch_bytes(n);
+    *bytes = sort > ploc ? sort : ploc;
     return hipSuccess;
+}
+
+// Binary tree by PLOC over the leaf boxes of the Morton order in a.leafbox;
+// afterwards the leaves are renumbered depth first (a.order rewritten) and
+// nodes, leaf_parent and brange describe the tree in that order.  The whole
+// scratch is reused (the sort is over).
+static hipError_t ploc_tree(BuildArgs& a, void* scratch, hipStream_t st)
+{
+    const int n = a.n;
+    const int nint = n - 1;
+    char* p = static_cast<char*>(scratch);
+    auto take = [&](size_t bytes) {
+        char* r = p;
+        p += (bytes + 255) & ~static_cast<size_t>(255);
+        return r;
+    };
+    int* refA = reinterpret_cast<int*>(take(sizeof(int) * n));
+    int* refB = reinterpret_cast<int*>(take(sizeof(int) * n));
+    float* boxA = reinterpret_cast<float*>(take(sizeof(float) * 6 * n));
+    float* boxB = reinterpret_cast<float*>(take(sizeof(float) * 6 * n));
+    int* nn = reinterpret_cast<int*>(take(sizeof(int) * n));
+    uint32_t* keep = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * n));
+    uint32_t* counts = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * blocks_for(n, kPlocBlock)));
+    int* ctr = reinterpret_cast<int*>(take(2 * sizeof(int)));  // node counter, survivors
+
+    k_ploc_init<<<blocks_for(n, 256), 256, 0, st>>>(n, a.leafbox, refA, boxA);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = fill_u32(ctr, 2, 0u, st);
+    int m = n;
+    for (int iter = 0; e == hipSuccess && m > 1; ++iter) {
+        const int nb = blocks_for(m, kPlocBlock);
+        k_ploc_nn<<<nb, kPlocBlock, 0, st>>>(m, boxA, nn);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = fill_u32(ctr + 1, 1, 0u, st);
+        if (e != hipSuccess) break;
+        k_ploc_merge<<<nb, kPlocBlock, 0, st>>>(m, refA, boxA, nn, a.nodes, keep, counts, ctr, n - 2,
+                                                reinterpret_cast<uint32_t*>(ctr + 1));
+        k_scan_exclusive<<<1, 1024, 0, st>>>(counts, nb);
+        k_ploc_scatter<<<nb, kPlocBlock, 0, st>>>(m, keep, counts, refA, boxA, refB, boxB);
+        e = hipGetLastError();
+        int survivors = m;
+        if (e == hipSuccess) e = hipMemcpyAsync(&survivors, ctr + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        if (survivors >= m || iter > 4 * n) return hipErrorUnknown;  // no merge: cannot happen
+        m = survivors;
+        int* tr = refA;
+        refA = refB;
+        refB = tr;
+        float* tb = boxA;
+        boxA = boxB;
+        boxB = tb;
+    }
+    if (e != hipSuccess) return e;
+    // the cluster buffers are free again
+    int* first = refA;
+    uint32_t* order_new = reinterpret_cast<uint32_t*>(refB);
+    k_tree_offsets<<<blocks_for(nint, 256), 256, 0, st>>>(nint, a.nodes, first);
+    k_tree_renumber<<<blocks_for(nint, 256), 256, 0, st>>>(nint, a.nodes, first, a.order, order_new, a.leaf_parent,
+                                                           a.brange);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(a.order, order_new, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st);
+    return e;
 }
 
 __global__ void k_collapse_init(int* wide_src, int* front, int* counts)
@@ -645,6 +902,13 @@ hipError_t lbvh_build(BuildArgs& a, void* scratch, hipStream_t st)
     if (e != hipSuccess) return e;
     if (n == 1) {
         k_single_root<<<1, 1, 0, st>>>(a.nodes, a.leaf_parent, a.brange);
+    } else if (a.ploc) {
+        // leaf boxes in Morton order, then the clustering rewrites the order
+        k_records<<<blocks_for(n, 256), 256, 0, st>>>(n, a.order, a.mu, a.quat, a.scale, a.opac, a.alpha_min,
+                                                        a.sigma, a.rec, a.leafbox);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = ploc_tree(a, scratch, st);
+        if (e != hipSuccess) return e;
     } else {
         k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(n, k0, a.nodes, a.leaf_parent, a.brange);
     }

@@ -195,7 +195,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
     for (int c = 0; c < FM; ++c) acc[c] = 0.0f;
     int nh = 0;
     uint64_t after = 0;          // resume key; while compositing, the key just composited
-    uint64_t pend = kKeyNone;    // hit key waiting for the insert step (mode kIns)
+    uint64_t pend = kKeyNone;    // hit key entering the buffer at the next iteration (mode kIns)
     bool round_full = false, term = false;
     int cur = kItemEmpty;
     int mode = kFetch;
@@ -208,17 +208,31 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         return kItemEmpty;
     };
     while (true) {
+        // Hits found by the previous leaf step enter the buffer first,
+        // predicated over the wave (the buffer is modified outside any
+        // divergent region, so it needs no per-branch copy); the branch on
+        // the ballot is wave-uniform and costs no memory round trip.
+        const bool want_ins = mode == kIns;
+        if (__ballot(want_ins)) {
+            const uint64_t ev = kb.insert_if(want_ins, pend);
+            if (want_ins) {
+                ++ct.inserts;
+                if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
+                pend = kKeyNone;
+                mode = kTrav;
+            }
+        }
         // Phase vote: the wave runs, per iteration, only the kind of step the
         // most lanes are waiting for (wave-uniform branch); the rest wait.
+        // Node and leaf steps stay apart: each memory instruction of a step
+        // then fetches one kind of data.
         const bool want_node = mode == kTrav && cur != kItemEmpty && cur >= 0;
         const bool want_leaf = mode == kTrav && cur < 0;
-        const bool want_ins = mode == kIns;
-        const bool want_other = mode != kDead && !want_ins && !want_node && !want_leaf;
-        const uint64_t bn = __ballot(want_node), bl = __ballot(want_leaf), bi = __ballot(want_ins),
-                       bo = __ballot(want_other);
-        if ((bn | bl | bi | bo) == 0) break;
-        const int cn = __popcll(bn), cl = __popcll(bl), ci = __popcll(bi), co = __popcll(bo);
-        if (cn >= cl && cn >= ci && cn >= co) {
+        const bool want_other = mode != kDead && !want_node && !want_leaf;
+        const uint64_t bn = __ballot(want_node), bl = __ballot(want_leaf), bo = __ballot(want_other);
+        if ((bn | bl | bo) == 0) break;
+        const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
+        if (cn >= cl && cn >= co) {
             if (want_node) {
                 ++ct.nodes;
                 const float4* np = reinterpret_cast<const float4*>(src.view(lr).wnodes + cur);
@@ -261,12 +275,12 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 if (key[1] < inf) st.push(ref[1]);
                 cur = key[0] < inf ? ref[0] : next_item();
             }
-        } else if (cl >= ci && cl >= co) {
+        } else if (cl >= co) {
             // Test the next surfels of the current cluster: both records of
             // a pair are fetched together (one memory round trip), the
             // second is tested only if the first does not enter the buffer.
-            // A hit for the buffer waits in `pend` for an insert step, which
-            // the wave runs once enough lanes hold one.
+            // A hit for the buffer waits in `pend` and is inserted at the top
+            // of the next iteration.
             if (want_leaf) {
                 const int first = (cur & ~kLeafBit) >> 4;
                 const int cnt = (cur & 15) + 1;
@@ -295,16 +309,6 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     pend = key;
                     mode = kIns;
                 }
-            }
-        } else if (ci >= co) {
-            // Insert step, predicated over the wave (the buffer is modified
-            // outside any divergent region, so it needs no per-branch copy).
-            const uint64_t ev = kb.insert_if(want_ins, pend);
-            if (want_ins) {
-                ++ct.inserts;
-                if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
-                pend = kKeyNone;
-                mode = kTrav;
             }
         } else if (want_other) {
             if (mode == kFetch) {

@@ -74,11 +74,15 @@ class TraceConfig:
 
 
 class Scene:
-    """A set of surfels plus its LBVH.  The parameter tensors are borrowed:
-    keep them alive, and call ``refit()`` after changing them in place."""
+    """A set of surfels plus its BVH.  The parameter tensors are borrowed:
+    keep them alive, and call ``refit()`` after changing them in place.
+    ``builder``: "radix" (default; Karras' radix tree over the Morton codes)
+    or "ploc" (clustering by union surface area: fewer surfel tests per ray,
+    slower build and refit)."""
 
     def __init__(self, mu, quat, scale, opacity, feat, alpha_min: float = DEFAULT_ALPHA_MIN,
-                 support_sigma: float = DEFAULT_SIGMA, build: bool = True, leaf_size: int = 0):
+                 support_sigma: float = DEFAULT_SIGMA, build: bool = True, leaf_size: int = 0,
+                 builder: str = "radix"):
         n = mu.shape[0]
         F = feat.shape[1] if feat.dim() == 2 else 1
         self.device = mu.device
@@ -86,6 +90,9 @@ class Scene:
         self.alpha_min = float(alpha_min)
         self.support_sigma = float(support_sigma)
         self.leaf_size = int(leaf_size)
+        if builder not in ("ploc", "radix"):
+            raise ValueError(f"unknown builder {builder!r}")
+        self.builder = builder
         self._set_tensors(mu, quat, scale, opacity, feat)
         h = ctypes.c_void_p()
         check(_lib.lib().irgs_scene_create(self.n, self.F, ctypes.byref(self._surfels()), ctypes.byref(h)),
@@ -124,7 +131,7 @@ class Scene:
 
     def build(self):
         with torch.cuda.device(self.device):
-            p = self.params(TraceConfig())
+            p = self.params(TraceConfig(), _lib.FLAG_PLOC_TREE if self.builder == "ploc" else 0)
             check(_lib.lib().irgs_scene_build(self.handle, ctypes.byref(p), _stream_handle(self.device)),
                   "irgs_scene_build")
         self.built = True

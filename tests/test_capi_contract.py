@@ -97,7 +97,7 @@ def test_packed_rejects_bad_arguments(L):
 
 def test_sizes_are_reported(L):
     a = L.irgs_scene_bytes(1_000_000, 8)
-    assert 100e6 < a < 400e6
+    assert 100e6 < a < 600e6     # records, binary + wide trees, and the transient build scratch
     assert L.irgs_scene_bytes(0, 8) >= 0
     assert L.irgs_trace_bytes(0, 8, 0) == 0
     assert L.irgs_trace_bytes(4_194_304, 8, 2) > L.irgs_trace_bytes(4_194_304, 8, 0)

@@ -23,7 +23,8 @@ def c1():
 
 def run(scene_np, ro, rd, hit_cap=256, **kw):
     from paper_2412_15867_amd import trace
-    scene = make_scene(scene_np, **{k: kw.pop(k) for k in ("alpha_min", "support_sigma", "leaf_size") if k in kw})
+    scene = make_scene(scene_np, **{k: kw.pop(k) for k in ("alpha_min", "support_sigma", "leaf_size", "builder")
+                                    if k in kw})
     res = trace(scene, dev(ro), dev(rd), hit_cap=hit_cap, **kw)
     torch.cuda.synchronize()
     out = to_np(res)
@@ -43,15 +44,40 @@ def test_c1_bvh_matches_oracle(c1):
     assert st["hits"] > 10000
 
 
-def test_c1_brute_force_equals_bvh_bitwise(c1):
+@pytest.mark.parametrize("builder", ["ploc", "radix"])
+def test_c1_brute_force_equals_bvh_bitwise(c1, builder):
+    """Both trees find every hit: the BVH trace equals the brute-force trace
+    over the same record order bit for bit."""
     sc, ro, rd = c1
-    note("c1 brute vs bvh")
-    a = run(sc, ro, rd, k=16, brute_force=True)
-    b = run(sc, ro, rd, k=16)
+    note(f"c1 brute vs bvh, {builder} tree")
+    a = run(sc, ro, rd, k=16, brute_force=True, builder=builder)
+    b = run(sc, ro, rd, k=16, builder=builder)
     for key in ("O", "F", "D", "T", "n_hits"):
         assert np.array_equal(a[key], b[key]), key
     m = np.arange(256)[None, :] < a["n_hits"][:, None]
     assert np.array_equal(np.where(m, a["hit_ids"], -1), np.where(m, b["hit_ids"], -1))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 17])
+@pytest.mark.parametrize("builder", ["ploc", "radix"])
+def test_tiny_scenes_both_builders(n, builder):
+    """Scenes of a few surfels (one of them invalid from n = 5 on): the tree
+    finds what the brute-force trace finds, bit for bit."""
+    g = np.random.default_rng(40 + n)
+    mu = g.uniform(-0.3, 0.3, (n, 3)).astype(np.float32)
+    q = g.standard_normal((n, 4)).astype(np.float32)
+    s = g.uniform(0.1, 0.4, (n, 2)).astype(np.float32)
+    o = g.uniform(0.3, 0.99, n).astype(np.float32)
+    f = g.uniform(0, 1, (n, 3)).astype(np.float32)
+    if n >= 5:
+        s[2] = 0.0
+    ro, rd = synth.pinhole_rays(16, 16)
+    note(f"tiny n={n} {builder}")
+    a = run((mu, q, s, o, f), ro, rd, k=4, brute_force=True, builder=builder)
+    b = run((mu, q, s, o, f), ro, rd, k=4, builder=builder)
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["n_hits"].sum() > 0
 
 
 @pytest.mark.parametrize("leaf", [1, 3, 16])
@@ -244,14 +270,15 @@ def test_surface_200k_full_launch_sampled(surface200k):
     assert 0.05 < frac_hit < 1.0
 
 
-def test_lbvh_structure(surface200k):
+@pytest.mark.parametrize("builder", ["ploc", "radix"])
+def test_lbvh_structure(surface200k, builder):
     """Every leaf is reached exactly once from the root, parents are
     consistent, node boxes contain their children's boxes and each leaf box
-    contains its surfel's support ellipse."""
+    contains its surfel's support ellipse (both tree builders)."""
     sc, _, _ = surface200k
     small = sc.subset(np.arange(0, 200_000, 7))
-    note("lbvh structure")
-    scene = make_scene(small)
+    note(f"lbvh structure, {builder} tree")
+    scene = make_scene(small, builder=builder)
     order, nodes, parent = (t.cpu().numpy() for t in scene.export())
     info = scene.info()
     scene.close()
