@@ -172,7 +172,7 @@ def run_c3(args):
     gO_d, gF_d, gD_d = t(gO), t(gF), t(gD)
     torch.cuda.synchronize()
     b0 = time.perf_counter()
-    scene = Scene(*[p.detach() for p in params], builder=args.builder)
+    scene = Scene(*[p.detach() for p in params], builder=args.builder, leaf_size=args.leaf_size)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - b0) * 1e3
     scene.set_params(*params)
@@ -302,7 +302,7 @@ def run_forward_only(args, small: bool):
         name = "200000 surfels (8 spheres + 4 planes, F=8), 256x256x64 MC rays, forward"
         n_brute = 16384
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    scene = Scene(*(t(a) for a in sc.astuple()), builder=args.builder)
+    scene = Scene(*(t(a) for a in sc.astuple()), builder=args.builder, leaf_size=args.leaf_size)
     ro_d, rd_d = t(ro), t(rd)
     R = ro.shape[0]
     cfg = TraceConfig(k=args.k)
@@ -355,7 +355,7 @@ def run_serve(args):
     scenes = []
     for n in sizes:
         sc = synth.surface_scene(n, F=8, lay=lay)
-        scenes.append(Scene(*(t(a) for a in sc.astuple()), builder=args.builder))
+        scenes.append(Scene(*(t(a) for a in sc.astuple()), builder=args.builder, leaf_size=args.leaf_size))
         del sc
     ro, rd = synth.mc_rays(256 * 256, 64, lay=lay)
     pool_o, pool_d = t(ro), t(rd)
@@ -429,7 +429,7 @@ def run_c5(args):
     gF = torch.randn((R, 8), device=dev, generator=gen)
     gD = torch.randn(R, device=dev, generator=gen)
     b0 = time.perf_counter()
-    scene = Scene(*params, builder=args.builder)
+    scene = Scene(*params, builder=args.builder, leaf_size=args.leaf_size)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - b0) * 1e3
     cfg = TraceConfig(k=args.k, recompute=args.recompute)
@@ -495,7 +495,7 @@ def run_pbr(args):
     mats = [t(px[k]).requires_grad_(True) for k in ("albedo", "rough", "env")]
     x, n, wo, u = (t(px[k]) for k in ("x", "n", "wo", "u"))
     g_c = torch.from_numpy(np.random.default_rng(synth.SEED_PBR + 1).standard_normal((P, 3)).astype(np.float32)).to(dev)
-    scene = Scene(*[p.detach() for p in params], builder=args.builder)
+    scene = Scene(*[p.detach() for p in params], builder=args.builder, leaf_size=args.leaf_size)
     scene.set_params(*params)
     cfg = TraceConfig(k=args.k, sh=True, hit_cap=args.hit_cap)
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -565,7 +565,7 @@ def run_relight(args):
     feat[:, 3] = 0.1 + 0.9 * feat[:, 3]
     px = synth.shading_pixels(P, Nr, lay=lay)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
-    scene = Scene(t(sc.mu), t(sc.quat), t(sc.scale), t(sc.opac), t(feat), builder=args.builder)
+    scene = Scene(t(sc.mu), t(sc.quat), t(sc.scale), t(sc.opac), t(feat), builder=args.builder, leaf_size=args.leaf_size)
     x, n, wo, u, albedo, rough, env = (t(px[k]) for k in ("x", "n", "wo", "u", "albedo", "rough", "env"))
     strat = args.relight_sampling == "stratified"
     u3 = t(synth.sky_uniforms(P, Nr))
@@ -645,7 +645,8 @@ def main():
     ap.add_argument("--points", type=int, default=256 * 256)
     ap.add_argument("--dirs", type=int, default=64)
     ap.add_argument("--k", type=int, default=16)
-    ap.add_argument("--builder", default="radix", choices=["radix", "ploc"],
+    ap.add_argument("--leaf-size", type=int, default=0, help="surfels per leaf cluster (0: the library default)")
+    ap.add_argument("--builder", default="ploc", choices=["ploc", "radix"],
                     help="binary tree under the 4-wide BVH: PLOC clustering or the Morton radix tree")
     ap.add_argument("--hit-cap", type=int, default=256)
     ap.add_argument("--recompute", action="store_true")

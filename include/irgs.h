@@ -72,7 +72,7 @@ typedef struct {
  *   t_min, t_max  hits need t_min < tau < t_max
  *   support_sigma hits need u^2 + v^2 <= support_sigma^2
  *   flags         IRGS_FLAG_* below
- *   leaf_size     build only: surfels per BVH leaf cluster, 1..16 (0 = 4)
+ *   leaf_size     build only: surfels per BVH leaf cluster, 1..16 (0 = 8)
  * alpha_min and support_sigma are fixed at build time (they size the boxes);
  * tracing with other values returns IRGS_E_STATE. */
 typedef struct {
@@ -106,14 +106,14 @@ typedef struct {
  * IRGS_FLAG_SH; k must be 16 or 32; not for the backward or the packed
  * launch. */
 #define IRGS_FLAG_NORMAL 8u
-/* scene build only: the binary tree under the 4-wide BVH comes from PLOC
- * clustering (Meister and Bittner 2018: mutually nearest clusters by union
- * surface area within 8 positions of the Morton order merge, iterated; the
- * leaves are then renumbered depth first) instead of Karras' radix tree over
- * the sorted Morton codes (the default).  Both trees give the same hits; the
- * PLOC tree bounds them with less box area, so traversals test fewer
- * surfels, at a slower build and refit. */
-#define IRGS_FLAG_PLOC_TREE 16u
+/* scene build only: the binary tree under the 4-wide BVH is Karras' radix
+ * tree over the sorted Morton codes (leaves stay in Morton order) instead
+ * of the default PLOC clustering (Meister and Bittner 2018: mutually
+ * nearest clusters by union surface area within 8 positions of the Morton
+ * order merge, iterated; the leaves are then renumbered depth first).  Both
+ * trees give the same hits; the PLOC tree bounds them with less box area,
+ * so traversals test fewer surfels, at a slower build. */
+#define IRGS_FLAG_RADIX_TREE 16u
 
 /* Outputs of a trace, caller-allocated (R = number of rays):
  *   opacity (R)      accumulated opacity O = sum T_i alpha_i (o_rt of Eq. 8;
@@ -191,7 +191,7 @@ irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, 
 irgs_status irgs_scene_set_params(irgs_scene scene, const irgs_surfels* params);
 
 /* Build: per-surfel records and support boxes, Morton codes, radix sort,
- * hierarchy (radix tree, or PLOC with IRGS_FLAG_PLOC_TREE), bottom-up
+ * hierarchy (PLOC, or the radix tree with IRGS_FLAG_RADIX_TREE), level-by-level
  * boxes, the 4-wide collapse.  Allocates the scene's device buffers on first
  * use.  Uses params->alpha_min, support_sigma, leaf_size and that flag.
  * Reads level sizes and the tree depth back (synchronises `stream`). */

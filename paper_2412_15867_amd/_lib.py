@@ -23,7 +23,7 @@ FLAG_BRUTE_FORCE = 1
 FLAG_RECOMPUTE = 2
 FLAG_SH = 4          # features are RGB SH coefficients; 3 composited channels
 FLAG_NORMAL = 8      # 3 more composited channels: the ray-facing normal (forward only)
-FLAG_PLOC_TREE = 16  # scene build: PLOC clustering instead of the Morton radix tree
+FLAG_RADIX_TREE = 16  # scene build: Morton radix tree instead of PLOC clustering
 
 
 class Surfels(ctypes.Structure):

@@ -38,7 +38,8 @@ struct irgs_scene_s {
     int n_wide = 0;
     int wide_depth = 0;
     int leaf_size = kLeafDefault;
-    bool ploc = false;
+    bool ploc = true;
+    std::vector<int> levels;  // level offsets of the refit (host)
 };
 
 namespace {
@@ -146,6 +147,8 @@ BuildArgs build_args(irgs_scene s)
     a.nodes = s->nodes;
     a.leaf_parent = s->leaf_parent;
     a.counters = s->counters;
+    a.level_nodes = reinterpret_cast<int*>(s->counters);
+    a.levels = &s->levels;
     a.depth = s->depth;
     a.brange = s->brange;
     a.wnodes = s->wnodes;
@@ -417,7 +420,7 @@ irgs_status irgs_scene_build(irgs_scene s, const irgs_params* p, void* stream)
         return fail(IRGS_E_INVALID, "alpha_min >= 0 and support_sigma > 0 required");
     if (p->leaf_size < 0 || p->leaf_size > 16) return fail(IRGS_E_INVALID, "leaf_size %d out of [0, 16]", p->leaf_size);
     s->leaf_size = p->leaf_size == 0 ? kLeafDefault : p->leaf_size;
-    s->ploc = (p->flags & IRGS_FLAG_PLOC_TREE) != 0;
+    s->ploc = (p->flags & IRGS_FLAG_RADIX_TREE) == 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = s->n;
     hipError_t e = hipSuccess;

@@ -1,6 +1,8 @@
 // Host-side interfaces between the translation units of the HIP library.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -24,7 +26,9 @@ struct BuildArgs {
     float* leafbox;         // 6 floats per Morton position
     BvhNode* nodes;
     int* leaf_parent;
-    uint32_t* counters;
+    uint32_t* counters;     // unused by the level refit (kept for the buffer layout)
+    int* level_nodes;       // internal node ids grouped by depth
+    std::vector<int>* levels;  // host: level offsets into level_nodes (depth + 2 entries)
     int* depth;             // device int: max number of internal ancestors of a leaf
     int2* brange;           // per binary node: first leaf, leaf count
     WideNode* wnodes;       // up to max(N - 1, 1) wide nodes

@@ -14,7 +14,8 @@
 //      per-tile histograms, one scan, stable wave-ballot ranking;
 //   4. Karras' hierarchy (longest common prefix of adjacent codes, index
 //      tie-break for equal codes);
-//   5. bottom-up boxes with per-node arrival counters (second arrival unions).
+//   5. node boxes level by level from the deepest (nodes grouped by depth
+//      once per build; one launch per level, no atomics).
 // Refit repeats 1 (in the existing leaf order) and 5 with the topology kept.
 #include <hip/hip_runtime.h>
 
@@ -374,46 +375,66 @@ __device__ __forceinline__ void node_union(const BvhNode& nd, float* out)
     }
 }
 
-__device__ __forceinline__ void store_child_box(BvhNode* nd, int which, const float* b)
+// ---------------------------------------------------------------- levels
+// The refit goes up the tree one depth level per launch (deepest first):
+// the kernel boundary orders a level's writes before the next level's
+// reads, so no atomics or cross-XCD cache maintenance are needed.  The
+// nodes are grouped by depth once per build.
+__global__ void k_node_depth(int nint, const BvhNode* __restrict__ nodes, int* __restrict__ ndepth,
+                             int* __restrict__ maxd)
 {
-    float* f = reinterpret_cast<float*>(nd);
-    const int o = which == 0 ? 0 : 6;
-    for (int k = 0; k < 6; ++k) __hip_atomic_store(f + o + k, b[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nint) return;
+    int d = 0;
+    for (int p = nodes[x].ch.z; p >= 0; p = nodes[p].ch.z) ++d;
+    ndepth[x] = d;
+    atomicMax(maxd, d);
 }
 
-__device__ __forceinline__ BvhNode load_node_coherent(BvhNode* nd)
+__global__ void k_level_hist(int nint, const int* __restrict__ ndepth, int* __restrict__ hist)
 {
-    BvhNode r;
-    float* f = reinterpret_cast<float*>(nd);
-    float* o = reinterpret_cast<float*>(&r);
-    for (int k = 0; k < 12; ++k) o[k] = __hip_atomic_load(f + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    r.ch = nd->ch;
-    return r;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < nint) atomicAdd(&hist[ndepth[x]], 1);
 }
 
-// Each leaf walks up; the second thread to arrive at a node writes the
-// node's box into its parent's slot and continues, the first one stops.
-__global__ void k_bottom_up(int n, const float* __restrict__ leafbox, BvhNode* nodes,
-                            const int* __restrict__ leaf_parent, uint32_t* counters)
+__global__ void k_level_scatter(int nint, const int* __restrict__ ndepth, int* __restrict__ cursor,
+                                int* __restrict__ level_nodes)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < nint) level_nodes[atomicAdd(&cursor[ndepth[x]], 1)] = x;
+}
+
+// Box b into slot `which` of node nd: six scalar stores, so that the two
+// children of a node (whose slots share a 16-byte word) never overwrite
+// each other's half.
+__device__ __forceinline__ void put_child_box(BvhNode* nd, int which, const float* b)
+{
+    float* f = reinterpret_cast<float*>(nd) + (which == 0 ? 0 : 6);
+    for (int k = 0; k < 6; ++k) f[k] = b[k];
+}
+
+__global__ void k_leaf_up(int n, const float* __restrict__ leafbox, BvhNode* __restrict__ nodes,
+                          const int* __restrict__ leaf_parent)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     float b[6];
     for (int k = 0; k < 6; ++k) b[k] = leafbox[6 * static_cast<int64_t>(p) + k];
-    int child = p | kLeafBit;
-    int node = leaf_parent[p];
-    while (node >= 0) {
-        const int which = (nodes[node].ch.x == child) ? 0 : 1;
-        store_child_box(&nodes[node], which, b);
-        const uint32_t prev =
-            __hip_atomic_fetch_add(&counters[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        const bool single = nodes[node].ch.y == kNoChild;
-        if (prev == 0 && !single) return;  // first arrival: the sibling finishes this node
-        const BvhNode nd = load_node_coherent(&nodes[node]);
-        node_union(nd, b);
-        child = node;
-        node = nd.ch.z;
-    }
+    const int node = leaf_parent[p];
+    put_child_box(&nodes[node], nodes[node].ch.x == (p | kLeafBit) ? 0 : 1, b);
+}
+
+// Every node of one level: the union of its two slots into its parent's.
+__global__ void k_level_up(int cnt, const int* __restrict__ ids, BvhNode* __restrict__ nodes)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const int x = ids[t];
+    const BvhNode nd = nodes[x];
+    float b[6];
+    node_union(nd, b);
+    const int parent = nd.ch.z;
+    put_child_box(&nodes[parent], nodes[parent].ch.x == x ? 0 : 1, b);
 }
 
 __global__ void k_depth(int n, const int* __restrict__ leaf_parent, const BvhNode* __restrict__ nodes,
@@ -836,19 +857,59 @@ __global__ void k_collapse_init(int* wide_src, int* front, int* counts)
     counts[1] = 0;
 }
 
-// Records + leaf boxes in the current leaf order, then bottom-up boxes.
+// Records + leaf boxes in the current leaf order, then the node boxes level
+// by level from the deepest (the levels are grouped at build time).
 static hipError_t refit_boxes(const BuildArgs& a, hipStream_t st)
 {
     const int n = a.n;
     k_records<<<blocks_for(n, 256), 256, 0, st>>>(n, a.order, a.mu, a.quat, a.scale, a.opac, a.alpha_min,
                                                     a.sigma, a.rec, a.leafbox);
+    k_leaf_up<<<blocks_for(n, 256), 256, 0, st>>>(n, a.leafbox, a.nodes, a.leaf_parent);
     hipError_t e = hipGetLastError();
+    const std::vector<int>& off = *a.levels;
+    for (int d = static_cast<int>(off.size()) - 2; e == hipSuccess && d >= 1; --d) {
+        const int cnt = off[d + 1] - off[d];
+        if (cnt <= 0) continue;
+        k_level_up<<<blocks_for(cnt, 256), 256, 0, st>>>(cnt, a.level_nodes + off[d], a.nodes);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// Internal nodes grouped by depth (root = depth 0): a.level_nodes holds their
+// ids level after level and *a.levels the level offsets (depth + 2 entries).
+// Uses the build scratch and reads the level sizes back (synchronises st).
+static hipError_t group_levels(BuildArgs& a, void* scratch, hipStream_t st)
+{
+    const int nint = a.n > 1 ? a.n - 1 : 1;
+    int* ndepth = static_cast<int*>(scratch);
+    int* maxd = ndepth + nint;
+    hipError_t e = fill_u32(maxd, 1, 0u, st);
     if (e != hipSuccess) return e;
-    const int nint = n > 1 ? n - 1 : 1;
-    e = fill_u32(a.counters, nint, 0u, st);
+    k_node_depth<<<blocks_for(nint, 256), 256, 0, st>>>(nint, a.nodes, ndepth, maxd);
+    int D = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&D, maxd, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
-    k_bottom_up<<<blocks_for(n, 256), 256, 0, st>>>(n, a.leafbox, a.nodes, a.leaf_parent, a.counters);
-    return hipGetLastError();
+    int* hist = maxd + 1;
+    e = fill_u32(hist, D + 1, 0u, st);
+    if (e != hipSuccess) return e;
+    k_level_hist<<<blocks_for(nint, 256), 256, 0, st>>>(nint, ndepth, hist);
+    std::vector<int> h(D + 1);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), hist, sizeof(int) * (D + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    std::vector<int>& off = *a.levels;
+    off.assign(D + 2, 0);
+    for (int d = 0; d <= D; ++d) off[d + 1] = off[d] + h[d];
+    e = hipMemcpyAsync(hist, off.data(), sizeof(int) * (D + 1), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    k_level_scatter<<<blocks_for(nint, 256), 256, 0, st>>>(nint, ndepth, hist, a.level_nodes);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host offsets outlive this call
+    return e;
 }
 
 hipError_t lbvh_build(BuildArgs& a, void* scratch, hipStream_t st)
@@ -913,6 +974,7 @@ hipError_t lbvh_build(BuildArgs& a, void* scratch, hipStream_t st)
         k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(n, k0, a.nodes, a.leaf_parent, a.brange);
     }
     e = hipGetLastError();
+    if (e == hipSuccess) e = group_levels(a, scratch, st);
     if (e != hipSuccess) return e;
     e = refit_boxes(a, st);
     if (e != hipSuccess) return e;

@@ -76,13 +76,13 @@ class TraceConfig:
 class Scene:
     """A set of surfels plus its BVH.  The parameter tensors are borrowed:
     keep them alive, and call ``refit()`` after changing them in place.
-    ``builder``: "radix" (default; Karras' radix tree over the Morton codes)
-    or "ploc" (clustering by union surface area: fewer surfel tests per ray,
-    slower build and refit)."""
+    ``builder``: "ploc" (default; clustering by union surface area: fewer
+    surfel tests per ray, slower build) or "radix" (Karras' radix tree over
+    the Morton codes)."""
 
     def __init__(self, mu, quat, scale, opacity, feat, alpha_min: float = DEFAULT_ALPHA_MIN,
                  support_sigma: float = DEFAULT_SIGMA, build: bool = True, leaf_size: int = 0,
-                 builder: str = "radix"):
+                 builder: str = "ploc"):
         n = mu.shape[0]
         F = feat.shape[1] if feat.dim() == 2 else 1
         self.device = mu.device
@@ -131,7 +131,7 @@ class Scene:
 
     def build(self):
         with torch.cuda.device(self.device):
-            p = self.params(TraceConfig(), _lib.FLAG_PLOC_TREE if self.builder == "ploc" else 0)
+            p = self.params(TraceConfig(), _lib.FLAG_RADIX_TREE if self.builder == "radix" else 0)
             check(_lib.lib().irgs_scene_build(self.handle, ctypes.byref(p), _stream_handle(self.device)),
                   "irgs_scene_build")
         self.built = True

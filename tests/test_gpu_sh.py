@@ -129,7 +129,9 @@ def test_sh_autograd_function(rays):
     res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=64)
     ref = trace_backward(scene, dev(ro), dev(rd), res, None, dev(gF), None, cfg=cfg)
     torch.cuda.synchronize()
-    torch.testing.assert_close(params[4].grad, ref["feat"], rtol=1e-5, atol=1e-7)
+    # the two launches add the same per-hit terms with FP32 atomics, in
+    # different orders
+    torch.testing.assert_close(params[4].grad, ref["feat"], rtol=1e-4, atol=1e-6)
     assert torch.count_nonzero(g1) == 0     # opacity upstream alone: no colour gradient
     scene.close()
 
