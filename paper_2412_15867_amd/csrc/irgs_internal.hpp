@@ -127,10 +127,24 @@ hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool u
 constexpr int kBwdCheckpoints = 8;
 constexpr int kBwdClaimWords = 64;
 inline int grad_stride(int F) { return ((10 + F + 31) / 32) * 32; }
+size_t sort_pairs_count_bytes(int n);
+hipError_t sort_pairs(int n, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint32_t* counts, int passes,
+                      hipStream_t st);
+// Ray order of the backward for gradients wider than its LDS table (rays
+// sorted by where they land): two key and two value buffers plus the sort's
+// tile counters, in words; none for launches too large for 32-bit indices.
+inline size_t ray_sort_words(int64_t R)
+{
+    if (R <= 0 || R > 0x7fffffffLL) return 0;
+    return (static_cast<size_t>(R) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) +
+            sort_pairs_count_bytes(static_cast<int>(R))) / sizeof(float) + 64;
+}
 inline size_t backward_scratch_words(int64_t R, int64_t N, int F)
 {
+    // the ray order is used only for gradients wider than the LDS table (the
+    // backward sorts exactly when F > 8: keep the two conditions the same)
     return static_cast<size_t>(trace_threads(R)) * kBwdCheckpoints * 4 + static_cast<size_t>(N) * grad_stride(F) +
-           kBwdClaimWords;
+           kBwdClaimWords + (F > 8 ? ray_sort_words(R) : 0);
 }
 hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int k, int64_t R,
                            const float* ro, const float* rd, const OutPtrs& saved, bool use_saved,

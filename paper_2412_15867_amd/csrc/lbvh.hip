@@ -767,6 +767,34 @@ hipError_t fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st)
     return hipGetLastError();
 }
 
+size_t sort_pairs_count_bytes(int n)
+{
+    return static_cast<size_t>(blocks_for(n, kSortTile)) * kRadixBins * sizeof(uint32_t);
+}
+
+// Stable LSD sort of (key, value) pairs on the low 8 * passes key bits; an
+// even number of passes leaves the result in k0 / v0.
+hipError_t sort_pairs(int n, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint32_t* counts, int passes,
+                      hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int ntiles = blocks_for(n, kSortTile);
+    for (int pass = 0; pass < passes; ++pass) {
+        k_radix_hist<<<ntiles, kSortThreads, 0, st>>>(n, pass * 8, k0, counts, ntiles);
+        k_scan_exclusive<<<1, 1024, 0, st>>>(counts, ntiles * kRadixBins);
+        k_radix_scatter<<<ntiles, kSortThreads, 0, st>>>(n, pass * 8, ntiles, k0, v0, k1, v1, counts);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t* tk = k0;
+        k0 = k1;
+        k1 = tk;
+        uint32_t* tv = v0;
+        v0 = v1;
+        v1 = tv;
+    }
+    return hipSuccess;
+}
+
 // PLOC scratch: two cluster buffers (reference + box), neighbours, survivor
 // flags, first leaves, the renumbered order, block counts and two counters.
 static size_t ploc_scratch_bytes(int n)

@@ -352,7 +352,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
                                                         const float* __restrict__ ro, const float* __restrict__ rd,
                                                         OutPtrs saved, bool use_saved, GradIn gin, float* gbuf,
                                                         int gs, int* ovf, int ovf_slots, float4* ck,
-                                                        unsigned long long* next_chunk)
+                                                        unsigned long long* next_chunk,
+                                                        const uint32_t* __restrict__ order)
 {
     __shared__ int hkeys[kHashSlots];
     __shared__ float hvals[kLdsComp * kValRow];
@@ -381,7 +382,9 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
         __syncthreads();
         const int64_t c = claimed;
         if (c >= chunks) break;
-        const int64_t r = c * kBwdBlock + tid;
+        // a chunk takes the next 64 rays of `order` or of the launch
+        const int64_t slot = c * kBwdBlock + tid;
+        const int64_t r = slot < R && order ? static_cast<int64_t>(order[slot]) : slot;
         Ray ray{};
         LaneUp<FU> up{};
         int nh = 0;
@@ -441,6 +444,48 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
     }
 }
 
+// Sort key of a ray for the backward's chunks: the Morton code (10 bits per
+// axis) of its mean hit point ro + (D / O) rd inside the root's box; a ray
+// without a hit sorts last.
+__global__ void k_ray_keys(int64_t R, const float* __restrict__ ro, const float* __restrict__ rd,
+                           const float* __restrict__ O, const float* __restrict__ D, const WideNode* __restrict__ root,
+                           uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (r >= R) return;
+    const float inf = __int_as_float(0x7f800000);
+    const float* w = reinterpret_cast<const float*>(root);  // lo_x[4], lo_y[4], lo_z[4], hi_x[4], hi_y[4], hi_z[4]
+    float lo[3] = {inf, inf, inf}, hi[3] = {-inf, -inf, -inf};
+    for (int c = 0; c < 4; ++c) {
+        if (w[c] == inf) continue;  // empty slot
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], w[4 * a + c]);
+            hi[a] = fmaxf(hi[a], w[12 + 4 * a + c]);
+        }
+    }
+    uint64_t key = 0xffffffffull;
+    const float o = O[r];
+    if (o > 0.0f && lo[0] <= hi[0]) {
+        const float t = D[r] / o;
+        uint32_t code = 0;
+        for (int a = 0; a < 3; ++a) {
+            const float x = fmaf(t, rd[3 * r + a], ro[3 * r + a]);
+            const float ext = hi[a] - lo[a];
+            const float u = ext > 0.0f ? (x - lo[a]) / ext : 0.0f;
+            const uint32_t q = static_cast<uint32_t>(fminf(fmaxf(u * 1024.0f, 0.0f), 1023.0f));
+            uint32_t v = q;  // spread 10 bits to every third position
+            v = (v | (v << 16)) & 0x030000ffu;
+            v = (v | (v << 8)) & 0x0300f00fu;
+            v = (v | (v << 4)) & 0x030c30c3u;
+            v = (v | (v << 2)) & 0x09249249u;
+            code |= v << (2 - a);
+        }
+        key = code;
+    }
+    keys[r] = key;
+    vals[r] = static_cast<uint32_t>(r);
+}
+
 // gbuf (interleaved per surfel) added into the caller's gradient arrays.
 __global__ void k_grad_out(int64_t n, int F, int gs, const float* __restrict__ gbuf, GradOut go)
 {
@@ -478,9 +523,31 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
     // zero the accumulator and the claim counter behind it
     hipError_t e = fill_u32(gbuf, static_cast<int64_t>(sc.n) * gs + kBwdClaimWords, 0u, st);
     if (e != hipSuccess) return e;
+    // Gradients wider than the LDS table (SH coefficients, F > 8) send most
+    // components straight to global atomics; their chunks then take rays in
+    // the order of where they land (stored lists with O and D), so that the
+    // surfels a block updates stay in L2 (at 1M surfels, SH degree 3: 95.6
+    // -> 81.6 ms; for F <= 8 the sort costs more than it saves).
+    const uint32_t* order = nullptr;
+    // (the condition on P.F is the one the scratch is sized by)
+    if (P.F > kLdsFeat && use_saved && saved.O && saved.D && ray_sort_words(R) > 0 && sc.n > 0) {
+        char* p = reinterpret_cast<char*>(next_chunk) + kBwdClaimWords * sizeof(float);
+        p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~static_cast<uintptr_t>(255));
+        uint64_t* k0 = reinterpret_cast<uint64_t*>(p);
+        uint64_t* k1 = k0 + R;
+        uint32_t* v0 = reinterpret_cast<uint32_t*>(k1 + R);
+        uint32_t* v1 = v0 + R;
+        uint32_t* counts = v1 + R;
+        k_ray_keys<<<static_cast<unsigned>((R + 255) / 256), 256, 0, st>>>(R, ro, rd, saved.O, saved.D, sc.wnodes, k0,
+                                                                             v0);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = sort_pairs(static_cast<int>(R), k0, v0, k1, v1, counts, 4, st);
+        if (e != hipSuccess) return e;
+        order = v0;
+    }
     const unsigned grid = persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH>, kBwdBlock));
     k_backward<K, FM, FU, SH><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf, gs, ovf,
-                                                  ovf_slots, reinterpret_cast<float4*>(ck), next_chunk);
+                                                  ovf_slots, reinterpret_cast<float4*>(ck), next_chunk, order);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t work = static_cast<int64_t>(sc.n) * (10 + P.F);

@@ -87,14 +87,17 @@ def grad_close(g_gpu, g_ref, rel=1e-3):
         assert err.max() <= rel, (name, err.max())
 
 
+@pytest.mark.parametrize("deg", [0, 1, 3])
 @pytest.mark.parametrize("recompute", [False, True])
-def test_sh_backward_matches_fp64_oracle(rays, recompute):
+def test_sh_backward_matches_fp64_oracle(rays, recompute, deg):
+    """Degree 0 (F = 3) runs the SH kernel without the ray order, degrees 1
+    and 3 (F = 12, 48) with it (stored lists)."""
     from paper_2412_15867_amd import TraceConfig, trace, trace_backward
     ro, rd = rays
     ro, rd = ro[::4], rd[::4]
-    surf = sh_cube(3)
+    surf = sh_cube(deg)
     gO, gF, gD, _ = synth.upstream(ro.shape[0], 3)
-    note(f"sh backward recompute={recompute}")
+    note(f"sh backward deg={deg} recompute={recompute}")
     scene = make_scene(surf)
     cfg = TraceConfig(k=16, sh=True, recompute=recompute)
     res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=256)
@@ -105,7 +108,7 @@ def test_sh_backward_matches_fp64_oracle(rays, recompute):
     scene.close()
     H = fwd["hit_ids"].shape[1]
     lists = np.where(np.arange(H)[None, :] < fwd["n_hits"][:, None], fwd["hit_ids"], -1)
-    ref = ograd.grad_given_hits(surf.astuple(), ro, rd, lists, gO, gF, gD, sh_deg=3)
+    ref = ograd.grad_given_hits(surf.astuple(), ro, rd, lists, gO, gF, gD, sh_deg=deg)
     grad_close(g, ref)
     assert np.abs(g["feat"]).max() > 0
 
