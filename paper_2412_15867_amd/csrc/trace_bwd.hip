@@ -26,7 +26,7 @@ namespace irgs {
 namespace {
 
 constexpr int kBwdBlock = 64;    // one wave per block: one table per 64 consecutive rays
-constexpr int kHashBits = 8;
+constexpr int kHashBits = 6;       // 64 slots: a small table leaves LDS for more resident waves
 constexpr int kHashSlots = 1 << kHashBits;
 constexpr int kHashProbes = 8;
 constexpr int kHashFill = kHashSlots * 3 / 4;  // no new keys once this many slots are taken
@@ -347,8 +347,18 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
     }
 }
 
-template <int K, int FM, int FU, bool SH>
-__global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
+// RM = false: rays whose stored hit list is complete, walked back to front
+// (the re-march code is compiled out, which keeps the register count low);
+// RM = true: the other rays (no stored lists, or a list cut at H_cap),
+// re-marched.  A backward runs the first over every ray when lists are
+// stored, then the second.
+// The walk over stored lists is latency-bound: it is held to the registers
+// of 3 waves per SIMD (no spills for F <= 16), and the LDS table is sized so
+// that LDS allows as many (measured at 1M surfels, F = 8: 256 slots and 2
+// waves 33.3 ms; 64 slots and 3 waves 24.5 ms; no table 28.0 ms).
+template <int K, int FM, int FU, bool SH, bool RM>
+__global__ __launch_bounds__(kBwdBlock) __attribute__((amdgpu_waves_per_eu(!RM && FM <= 16 ? 3 : 1)))
+void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                         const float* __restrict__ ro, const float* __restrict__ rd,
                                                         OutPtrs saved, bool use_saved, GradIn gin, float* gbuf,
                                                         int gs, int* ovf, int ovf_slots, float4* ck,
@@ -394,11 +404,12 @@ __global__ __launch_bounds__(kBwdBlock) void k_backward(SceneView sc, RawSurfels
             up = load_upstream<FU>(gin, r, SH ? 3 : P.F);
             const int nh_saved = saved.n_hits ? saved.n_hits[r] : -1;
             if (up.any && sc.n > 0 && ray_valid(ray) && nh_saved != 0) {
-                if (use_saved && nh_saved > 0 && nh_saved <= saved.H_cap) {
-                    stored = true;
-                    nh = nh_saved;
+                const bool complete = use_saved && nh_saved > 0 && nh_saved <= saved.H_cap;
+                if constexpr (!RM) {
+                    stored = complete;
+                    nh = complete ? nh_saved : 0;
                 } else {
-                    bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr);
+                    if (!complete) bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr);
                 }
             }
         }
@@ -545,9 +556,20 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
         if (e != hipSuccess) return e;
         order = v0;
     }
-    const unsigned grid = persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH>, kBwdBlock));
-    k_backward<K, FM, FU, SH><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf, gs, ovf,
-                                                  ovf_slots, reinterpret_cast<float4*>(ck), next_chunk, order);
+    if (use_saved) {
+        const unsigned grid =
+            persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, false>, kBwdBlock));
+        k_backward<K, FM, FU, SH, false><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin,
+                                                                     gbuf, gs, ovf, ovf_slots,
+                                                                     reinterpret_cast<float4*>(ck), next_chunk, order);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // rays without a complete stored list (all of them without stored lists)
+    const unsigned grid = persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, true>, kBwdBlock));
+    k_backward<K, FM, FU, SH, true><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf,
+                                                                gs, ovf, ovf_slots, reinterpret_cast<float4*>(ck),
+                                                                next_chunk + 1, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t work = static_cast<int64_t>(sc.n) * (10 + P.F);
