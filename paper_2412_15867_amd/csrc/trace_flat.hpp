@@ -97,6 +97,14 @@ __device__ __forceinline__ int64_t claim_slot(unsigned long long* next)
     return static_cast<int64_t>(base) + rank;
 }
 
+// Stored hit lists are written two entries at a time (one 8-byte store for
+// the ids, one for the transmittances) when rows start 8-byte aligned.
+__device__ __forceinline__ bool pair_stores(const OutPtrs& out)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(out.hit_ids) | reinterpret_cast<uintptr_t>(out.hit_T);
+    return (out.H_cap & 1) == 0 && (a & 7) == 0;
+}
+
 template <int FM, int CM, class Source>
 __device__ __forceinline__ void write_result(const Source& src, const LaneRay& lr, float O, float D, float T,
                                              const float* acc, int nh, const Counters& ct)
@@ -196,6 +204,8 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
     int nh = 0;
     uint64_t after = 0;          // resume key; while compositing, the key just composited
     uint64_t pend = kKeyNone;    // hit key entering the buffer at the next iteration (mode kIns)
+    int pend_id = 0;             // stored hit list: an even entry waiting for its pair
+    float pend_T = 0.0f;
     bool round_full = false, term = false;
     int cur = kItemEmpty;
     int mode = kFetch;
@@ -354,13 +364,27 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 add_features<FM, CM>(src.view(lr), P, ray, id, s.b, w, acc);
                 const OutPtrs& out = src.out(lr);
                 if (out.hit_ids && nh < out.H_cap) {
-                    out.hit_ids[lr.r * out.H_cap + nh] = id;
-                    if (out.hit_T) out.hit_T[lr.r * out.H_cap + nh] = T;
+                    const int64_t at = lr.r * out.H_cap + nh;
+                    if (!pair_stores(out)) {
+                        out.hit_ids[at] = id;
+                        if (out.hit_T) out.hit_T[at] = T;
+                    } else if (nh & 1) {  // the second of a pair: both in one 8-byte store each
+                        *reinterpret_cast<int2*>(out.hit_ids + at - 1) = make_int2(pend_id, id);
+                        if (out.hit_T) *reinterpret_cast<float2*>(out.hit_T + at - 1) = make_float2(pend_T, T);
+                    } else {
+                        pend_id = id;
+                        pend_T = T;
+                    }
                 }
                 T = T * (1.0f - a);
                 ++nh;
                 if (T < P.T_min) term = true;
             } else if (term || !round_full) {
+                const OutPtrs& out = src.out(lr);
+                if (out.hit_ids && pair_stores(out) && (nh & 1) && nh - 1 < out.H_cap) {  // unpaired last entry
+                    out.hit_ids[lr.r * out.H_cap + nh - 1] = pend_id;
+                    if (out.hit_T) out.hit_T[lr.r * out.H_cap + nh - 1] = pend_T;
+                }
                 write_result<FM, CM>(src, lr, O, D, T, acc, nh, ct);
                 mode = kFetch;
             } else {

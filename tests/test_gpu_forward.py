@@ -94,6 +94,23 @@ def test_leaf_size_does_not_change_the_result(c1, leaf):
     assert np.array_equal(np.where(m, a["hit_ids"], -1), np.where(m, b["hit_ids"], -1))
 
 
+@pytest.mark.parametrize("cap", [33, 34])
+def test_hit_list_capacity_odd_and_even(c1, cap):
+    """Stored lists go out two entries per store for an even capacity and
+    one per store for an odd one; either way a shorter capacity stores the
+    first entries of the full list (ids and transmittances)."""
+    sc, ro, rd = c1
+    note(f"c1 hit_cap={cap}")
+    a = run(sc, ro, rd, k=16, hit_cap=256)
+    b = run(sc, ro, rd, k=16, hit_cap=cap)
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(a[key], b[key]), key
+    m = np.arange(cap)[None, :] < np.minimum(a["n_hits"], cap)[:, None]
+    for key in ("hit_ids", "hit_T"):
+        assert np.array_equal(np.where(m, a[key][:, :cap], 0), np.where(m, b[key], 0)), key
+    assert (a["n_hits"] % 2 == 1).any() and (a["n_hits"] > cap).any()
+
+
 @pytest.mark.parametrize("k", [1, 2, 4, 8, 32, 64])
 def test_k_does_not_change_the_result(c1, k):
     """Exact order + per-hit termination make the output independent of k
