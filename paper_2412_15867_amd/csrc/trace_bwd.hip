@@ -400,16 +400,19 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
         int nh = 0;
         bool stored = false;
         if (r < R) {
-            ray = load_ray(ro, rd, r);
-            up = load_upstream<FU>(gin, r, SH ? 3 : P.F);
+            // each instance loads only the rays it owns
             const int nh_saved = saved.n_hits ? saved.n_hits[r] : -1;
-            if (up.any && sc.n > 0 && ray_valid(ray) && nh_saved != 0) {
-                const bool complete = use_saved && nh_saved > 0 && nh_saved <= saved.H_cap;
-                if constexpr (!RM) {
-                    stored = complete;
-                    nh = complete ? nh_saved : 0;
-                } else {
-                    if (!complete) bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr);
+            const bool complete = use_saved && nh_saved > 0 && nh_saved <= saved.H_cap;
+            if (RM ? (!complete && nh_saved != 0) : complete) {
+                ray = load_ray(ro, rd, r);
+                up = load_upstream<FU>(gin, r, SH ? 3 : P.F);
+                if (up.any && sc.n > 0 && ray_valid(ray)) {
+                    if constexpr (!RM) {
+                        stored = true;
+                        nh = nh_saved;
+                    } else {
+                        bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr);
+                    }
                 }
             }
         }
