@@ -209,6 +209,30 @@ def run_c3(args):
     bwd_ms = np.array([e[2].elapsed_time(e[3]) for e in events])
     step_ms = wall * 1e3 / args.steps
 
+    # The same step with a 32-entry k-buffer: k only changes the number of
+    # rounds, never the result (same hits, same order), so this times the
+    # identical computation at the other buffer size.
+    alt = None
+    if args.k == 16 and not args.no_k32:
+        cfg_main = cfg
+        cfg = TraceConfig(k=32, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh)
+        step(False)
+        torch.cuda.synchronize()
+        ev32 = []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            ev32.append(step(True))
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
+        o32 = trace(scene, ro_d, rd_d, cfg, hit_cap=0)
+        o16 = trace(scene, ro_d, rd_d, cfg_main, hit_cap=0)
+        same = all(torch.equal(getattr(o16, k), getattr(o32, k)) for k in ("opacity", "feat", "depth", "T", "n_hits"))
+        alt = {"k": 32, "value": round(R / (ms32 * 1e-3) / 1e6, 3), "ms_per_step": round(ms32, 3),
+               "fwd_in_step_ms": round(float(np.median([e[1].elapsed_time(e[2]) for e in ev32])), 3),
+               "bwd_ms": round(float(np.median([e[2].elapsed_time(e[3]) for e in ev32])), 3),
+               "forward_output_bitwise_equal_to_k16": bool(same)}
+        cfg = cfg_main
+
     # hit statistics of this workload (the same forward, outputs kept)
     res = trace(scene, ro_d, rd_d, cfg, hit_cap=0)
     torch.cuda.synchronize()
@@ -251,6 +275,7 @@ def run_c3(args):
                                f"{'recompute' if args.recompute else 'store'} mode, {args.builder} tree",
                    "surfels": N, "rays": R, "features": F, "k": args.k, "tree": args.builder},
         "fwd_mrays_s": round(R / (fwd_only_ms * 1e-3) / 1e6, 3),
+        **({"k32": alt} if alt else {}),
         "fwd_ms": round(fwd_only_ms, 3),
         "fwd_in_step_ms": round(f_med, 3),
         "bwd_ms": round(b_med, 3),
@@ -644,7 +669,9 @@ def main():
     ap.add_argument("--surfels", type=int, default=1_000_000)
     ap.add_argument("--points", type=int, default=256 * 256)
     ap.add_argument("--dirs", type=int, default=64)
-    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--k", type=int, default=None,
+                    help="k-buffer size (default 16; 32 for the pbr and relight workloads)")
+    ap.add_argument("--no-k32", action="store_true", help="default workload: skip the same step timed at k = 32")
     ap.add_argument("--leaf-size", type=int, default=0, help="surfels per leaf cluster (0: the library default)")
     ap.add_argument("--builder", default="ploc", choices=["ploc", "radix"],
                     help="binary tree under the 4-wide BVH: PLOC clustering or the Morton radix tree")
@@ -657,6 +684,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 512 MiB device copy (for scaling profiled FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
+    if args.k is None:
+        args.k = 32 if args.workload in ("pbr", "relight") else 16
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the trace shards rays across GPUs with no exchange in the "
               "forward and one gradient all-reduce in the backward, which this single-GPU build does not "
