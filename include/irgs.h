@@ -230,7 +230,7 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
 irgs_status irgs_scene_info(irgs_scene scene, int64_t* n_internal, int32_t* max_depth);
 
 /* Copy the tree of a built scene into caller DEVICE buffers (any NULL is
- * skipped): order (N, int32: Morton position -> surfel id), nodes
+ * skipped): order (N, int32: leaf position -> surfel id), nodes
  * ((N-1) x 16 int32 words: 12 box floats as bits, child0, child1, parent,
  * 0), leaf_parent (N).  For structural tests. */
 irgs_status irgs_scene_export(irgs_scene scene, int32_t* order, int32_t* nodes, int32_t* leaf_parent,

@@ -25,7 +25,7 @@ constexpr int kStackLds = 24;        // per-lane traversal stack entries kept in
 constexpr int kLeafBit = 0x80000000; // child reference: leaf flag
 constexpr int kNoChild = -1;         // child reference: empty slot (N == 1 root)
 
-// 64-byte surfel record, stored in Morton (BVH leaf) order.
+// 64-byte surfel record, stored in BVH leaf order.
 //   a = (mu.xyz, o)            b = (n.xyz, rho2_max)
 //   c = (t_u / s_u, id bits)   d = (t_v / s_v, 0)
 // rho2_max = min(sigma^2, 2 ln(o / alpha_min)), or -1 for a surfel that can
@@ -36,7 +36,7 @@ struct __align__(16) SurfelRec {
 
 // Internal BVH node: the boxes of both children plus their references.
 // A reference r >= 0 is an internal node, r with kLeafBit set is the leaf at
-// Morton position (r & ~kLeafBit), kNoChild is an empty slot.
+// leaf position (r & ~kLeafBit), kNoChild is an empty slot.
 struct __align__(16) BvhNode {
     float4 p0;  // lo0.xyz, hi0.x
     float4 p1;  // hi0.yz, lo1.xy
@@ -47,7 +47,7 @@ struct __align__(16) BvhNode {
 // 4-wide node used by the traversal (collapsed from the binary tree), child
 // boxes stored per axis so the four slab tests share instructions.  A child
 // reference r >= 0 is a wide node; r with kLeafBit set is a cluster of
-// ((r & 15) + 1) surfels starting at Morton position ((r & ~kLeafBit) >> 4);
+// ((r & 15) + 1) surfels starting at leaf position ((r & ~kLeafBit) >> 4);
 // kNoChild is an empty slot (its box is all +inf).
 struct __align__(16) WideNode {
     float4 lo_x, lo_y, lo_z;
@@ -65,7 +65,7 @@ __host__ __device__ __forceinline__ int cluster_ref(int first, int count)
 
 // What a trace kernel needs of one scene (passed by value).
 struct SceneView {
-    const SurfelRec* rec;   // N records, Morton order
+    const SurfelRec* rec;   // N records, leaf order
     const WideNode* wnodes; // 4-wide nodes, root = 0
     const float* feat;      // N x F, caller layout (original ids)
     int32_t n;
@@ -155,7 +155,7 @@ __device__ __forceinline__ SurfelRec load_rec(const SurfelRec* __restrict__ rec,
     return s;
 }
 
-// Hit keys: (tau, Morton position) packed into one 64-bit integer whose
+// Hit keys: (tau, leaf position) packed into one 64-bit integer whose
 // unsigned order is the lexicographic order (the float maps to an unsigned
 // integer of the same order: sign-flipped when negative).
 __device__ __forceinline__ uint64_t hit_key(float tau, int pos)

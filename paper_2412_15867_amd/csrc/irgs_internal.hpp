@@ -20,10 +20,10 @@ struct BuildArgs {
     const float* opac;
     float alpha_min;
     float sigma;
-    uint32_t* order;        // Morton position -> surfel id
+    uint32_t* order;        // leaf position -> surfel id
     uint64_t* sorted_keys;  // optional copy of the sorted Morton codes
     SurfelRec* rec;
-    float* leafbox;         // 6 floats per Morton position
+    float* leafbox;         // 6 floats per leaf position
     BvhNode* nodes;
     int* leaf_parent;
     uint32_t* counters;     // unused by the level refit (kept for the buffer layout)

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(int n, int shift
 }
 
 // ---------------------------------------------------------------- records
-// Record + leaf box of the surfel at Morton position p.
+// Record + leaf box of the surfel at leaf position p.
 __global__ void k_records(int n, const uint32_t* __restrict__ order, const float* __restrict__ mu,
                           const float* __restrict__ quat, const float* __restrict__ scale,
                           const float* __restrict__ opac, float alpha_min, float sigma,
@@ -475,7 +475,7 @@ __device__ __forceinline__ void set_wide_box(WideNode* w, int slot, const float*
 // its up-to-four children are found by repeatedly opening the candidate with
 // the largest box area, as long as that candidate holds more than leaf_max
 // surfels.  Candidates with at most leaf_max surfels become cluster leaves
-// (their surfels are contiguous in Morton order); larger ones become new wide
+// (their surfels are contiguous in leaf order); larger ones become new wide
 // nodes of the next level.
 __global__ void k_collapse(int nfront, const int* __restrict__ front_in, int* __restrict__ front_out,
                            int* __restrict__ counts, int* __restrict__ wide_src, const BvhNode* __restrict__ bn,

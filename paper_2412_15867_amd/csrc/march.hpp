@@ -20,8 +20,8 @@ struct Counters {
     int nodes = 0, tests = 0, inserts = 0, rounds = 0;
 };
 
-// The k-buffer holds hit keys (tau, Morton position), ascending.  Equal
-// depths are ordered by Morton position, which every kernel shares.  alpha
+// The k-buffer holds hit keys (tau, leaf position), ascending.  Equal
+// depths are ordered by leaf position, which every kernel shares.  alpha
 // and the surfel id are re-read from the record when an entry is composited.
 template <int K>
 struct KBuf {
@@ -60,7 +60,7 @@ struct KBuf {
     }
 };
 
-// Offer the record at Morton position `pos` to the buffer: Eq. 6-7 test,
+// Offer the record at leaf position `pos` to the buffer: Eq. 6-7 test,
 // above the resume key, below the K-th key once full.
 template <int K>
 __device__ __forceinline__ void offer(KBuf<K>& kb, const SurfelRec& s, int pos, const Ray& ray, float t_min,

@@ -226,7 +226,7 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, const TraceParam
     h.g[6] = static_cast<float>((dz - z * proj) * inv);
 }
 
-// alpha of the k-buffer entry at Morton position pos (the same arithmetic as
+// alpha of the k-buffer entry at leaf position pos (the same arithmetic as
 // the forward composite, so T is reproduced bit for bit).
 __device__ __forceinline__ float entry_alpha(const SceneView& sc, const Ray& ray, int pos)
 {
