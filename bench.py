@@ -59,6 +59,20 @@ def forward_fingerprint() -> str:
     return h.hexdigest()[:16]
 
 
+def measured_l2_hit_rate():
+    """L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)) of the same in-step
+    forward launch from the committed rocprofv3 summary, or None (missing,
+    or taken on other kernel sources)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = next(json.loads(ln[len("traffic-data: "):]) for ln in fh if ln.startswith("traffic-data: "))
+    except (OSError, StopIteration):
+        return None
+    if d.get("kernel_fingerprint") != forward_fingerprint() or "tcc_hit" not in d:
+        return None
+    return round(d["tcc_hit"] / max(d["tcc_hit"] + d["tcc_miss"], 1.0), 4)
+
+
 def measured_traffic():
     """HBM-side bytes of one in-step forward launch from the committed
     rocprofv3 summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the
@@ -287,6 +301,7 @@ def run_c3(args):
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic() if dom_is_fwd and not sh else None,
+                     "l2_hit_rate": measured_l2_hit_rate() if dom_is_fwd and not sh else None,
                      "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": round(dom_ms, 3)},
         "roofline_fwd": {"achieved": round(fb / (fwd_only_ms * 1e-3) / 1e9, 3), "bytes": fb},
     }
