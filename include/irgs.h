@@ -183,7 +183,7 @@ size_t irgs_scene_bytes(int64_t n, int32_t F);
 size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags);
 
 /* Create a scene over borrowed parameters (no device work, no allocation
- * beyond the handle).  n >= 0, 1 <= F <= 64. */
+ * beyond the handle).  0 <= n <= 2^27 (134,217,728), 1 <= F <= 64. */
 irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, irgs_scene* out);
 
 /* Point the scene at other parameter buffers of the same shape (the tree

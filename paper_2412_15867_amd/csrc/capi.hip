@@ -389,7 +389,8 @@ irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, 
 {
     if (!out) return fail(IRGS_E_INVALID, "out is NULL");
     *out = nullptr;
-    if (n < 0 || n > (int64_t(1) << 30)) return fail(IRGS_E_INVALID, "n = %lld out of range", (long long)n);
+    // leaf references pack a position in 27 bits (cluster_ref: first << 4)
+    if (n < 0 || n > (int64_t(1) << 27)) return fail(IRGS_E_INVALID, "n = %lld out of range [0, 2^27]", (long long)n);
     if (F < 1 || F > kMaxF) return fail(IRGS_E_INVALID, "F = %d out of range [1, %d]", F, kMaxF);
     if (!params) return fail(IRGS_E_INVALID, "params is NULL");
     if (n > 0 && (!params->mu || !params->quat || !params->scale || !params->opacity || !params->feat))

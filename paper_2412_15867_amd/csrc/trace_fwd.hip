@@ -1,9 +1,11 @@
 // Forward 2D Gaussian ray tracing (Sec. 3.2, Eq. 2, 6-8) on gfx950.
 //
-// One lane traces one ray; a persistent grid strides over the rays.  Each
-// k-buffer round collects the K nearest hits after the resume key (by BVH
-// traversal, or by testing every record in the plain tracer), then
-// composites them front to back in registers:
+// One lane traces one ray at a time: with the BVH, through the flat state
+// machine of trace_flat.hpp (rays claimed per wave from a counter); the
+// plain tracer strides a persistent grid over the rays.  Each k-buffer
+// round collects the K nearest hits after the resume key (by BVH traversal,
+// or by testing every record in the plain tracer), then composites them
+// front to back in registers:
 //     w = T alpha;  O += w;  F += w f;  D += w tau;  T *= (1 - alpha)
 // and stops once T < T_min (the hit that crosses the cutoff is included).
 // A round with fewer than K hits is the last one.

@@ -57,6 +57,8 @@ def test_create_rejects_bad_arguments(L):
     assert b"F = 0" in L.irgs_last_error()
     assert L.irgs_scene_create(10, 65, ctypes.byref(s), ctypes.byref(h)) == _lib.IRGS_E_INVALID
     assert L.irgs_scene_create(-1, 3, ctypes.byref(s), ctypes.byref(h)) == _lib.IRGS_E_INVALID
+    # leaf references hold a 27-bit position
+    assert L.irgs_scene_create((1 << 27) + 1, 3, ctypes.byref(s), ctypes.byref(h)) == _lib.IRGS_E_INVALID
     s0 = _lib.Surfels(None, 1, 1, 1, 1)
     assert L.irgs_scene_create(10, 3, ctypes.byref(s0), ctypes.byref(h)) == _lib.IRGS_E_INVALID
     assert L.irgs_scene_create(10, 3, None, ctypes.byref(h)) == _lib.IRGS_E_INVALID
