@@ -97,13 +97,13 @@ typedef struct {
  * complex harmonics with the Condon-Shortley phase for m > 0 / m < 0); each
  * hit contributes, per channel, max(sum_j Y_j(d) k_j + 1/2, 0) with d the
  * normalised ray direction.  out->feat and grad_in->g_feat are then R x 3;
- * grads->feat stays N x F.  k must be 16 or 32; not for irgs_trace_packed. */
+ * grads->feat stays N x F.  k must be 16, 32 or 64; not for irgs_trace_packed. */
 #define IRGS_FLAG_SH 4u
 /* trace only (relighting: the trace alpha-blends albedo, roughness and the
  * normal): after the F <= 5 features, 3 more composited channels hold each
  * hit's unit normal, negated where it points along the ray (n . r_d > 0) so
  * that it faces the ray; out->feat is R x (F + 3).  Exclusive with
- * IRGS_FLAG_SH; k must be 16 or 32; not for the backward or the packed
+ * IRGS_FLAG_SH; k must be 16, 32 or 64; not for the backward or the packed
  * launch. */
 #define IRGS_FLAG_NORMAL 8u
 /* scene build only: the binary tree under the 4-wide BVH is Karras' radix

@@ -120,12 +120,12 @@ irgs_status check_params(const irgs_params* p, int32_t F)
     if (p->flags & IRGS_FLAG_SH) {
         if (sh_degree(F) < 0)
             return fail(IRGS_E_INVALID, "IRGS_FLAG_SH needs 3 (deg + 1)^2 features, deg <= 3 (3, 12, 27, 48); F = %d", F);
-        if (k != 16 && k != 32) return fail(IRGS_E_INVALID, "IRGS_FLAG_SH supports k = 16 or 32");
+        if (k != 16 && k != 32 && k != 64) return fail(IRGS_E_INVALID, "IRGS_FLAG_SH supports k = 16, 32 or 64");
     }
     if (p->flags & IRGS_FLAG_NORMAL) {
         if (p->flags & IRGS_FLAG_SH) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL and IRGS_FLAG_SH are exclusive");
         if (F > 5) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL supports F <= 5 (got %d)", F);
-        if (k != 16 && k != 32) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL supports k = 16 or 32");
+        if (k != 16 && k != 32 && k != 64) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL supports k = 16, 32 or 64");
     }
     return IRGS_OK;
 }

@@ -586,7 +586,7 @@ hipError_t launch_k(const SceneView& sc, const RawSurfels& raw, const TraceParam
                     const float* rd, const OutPtrs& saved, bool use_saved, const GradIn& gin, const GradOut& go,
                     int* ovf, int ovf_slots, float* ck, hipStream_t st)
 {
-    if constexpr (K == 16 || K == 32) {  // SH: 48 coefficient gradients, 3 upstream channels
+    if constexpr (K == 16 || K == 32 || K == 64) {  // SH: 48 coefficient gradients, 3 upstream channels
         if (P.sh_deg >= 0)
             return launch_kf<K, 48, 4, true>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
     }

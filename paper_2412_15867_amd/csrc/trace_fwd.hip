@@ -127,7 +127,7 @@ template <int K, bool BVH>
 hipError_t launch_k(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
                     const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
 {
-    if constexpr (K == 16 || K == 32) {
+    if constexpr (K == 16 || K == 32 || K == 64) {
         if (P.sh_deg >= 0) return launch_kf<K, 4, BVH, kColSH>(sc, P, R, ro, rd, out, fs, st);  // 3 colour channels
         if (P.normals) {
             if (P.F <= 5) return launch_kf<K, 8, BVH, kColNormal>(sc, P, R, ro, rd, out, fs, st);  // F + 3 channels

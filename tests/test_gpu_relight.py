@@ -47,11 +47,13 @@ def test_normal_channels_match_oracle_and_brute_force():
     g = to_np(trace(scene, dev(ro), dev(rd), TraceConfig(k=16, normals=True), hit_cap=256))
     b = to_np(trace(scene, dev(ro), dev(rd), TraceConfig(k=16, normals=True, brute_force=True), hit_cap=256))
     c = to_np(trace(scene, dev(ro), dev(rd), TraceConfig(k=32, normals=True), hit_cap=256))
+    e = to_np(trace(scene, dev(ro), dev(rd), TraceConfig(k=64, normals=True), hit_cap=256))
     scene.close()
     assert g["F"].shape == (ro.shape[0], 7)
     for key in ("O", "F", "D", "T", "n_hits"):
         assert np.array_equal(g[key], b[key]), key
         assert np.array_equal(g[key], c[key]), key     # k only changes the rounds
+        assert np.array_equal(g[key], e[key]), key
     validate(surf.astuple(), ro, rd, g, with_normal=True)
 
 

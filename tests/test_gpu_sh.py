@@ -52,13 +52,15 @@ def test_sh_forward_matches_oracle(rays, deg):
 def test_sh_brute_force_bvh_and_k_bitwise(rays):
     ro, rd = rays
     surf = sh_cube(3)
-    note("sh brute vs bvh vs k=32")
+    note("sh brute vs bvh vs k=32, 64")
     a = run(surf, ro, rd, k=16, brute_force=True)
     b = run(surf, ro, rd, k=16)
     c = run(surf, ro, rd, k=32)
+    e = run(surf, ro, rd, k=64)
     for key in ("O", "F", "D", "T", "n_hits"):
         assert np.array_equal(a[key], b[key]), key
         assert np.array_equal(b[key], c[key]), key
+        assert np.array_equal(b[key], e[key]), key
 
 
 def test_sh_degree0_is_a_constant_colour(rays):
@@ -150,7 +152,7 @@ def test_sh_argument_errors(rays):
     scene.close()
     scene = make_scene(sh_cube(1))
     with pytest.raises(_lib.IrgsError):
-        trace(scene, dev(ro), dev(rd), TraceConfig(k=8, sh=True))   # SH: k = 16 or 32
+        trace(scene, dev(ro), dev(rd), TraceConfig(k=8, sh=True))   # SH: k = 16, 32 or 64
     with pytest.raises(ValueError):
         trace_packed([scene], [(0, dev(ro), dev(rd), alloc_result(ro.shape[0], 3, scene.device))],
                      TraceConfig(k=16, sh=True))
