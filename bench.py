@@ -267,7 +267,9 @@ def run_c3(args):
     f_med, b_med = float(np.median(fwd_ms)), float(np.median(bwd_ms))
     dom_is_fwd = f_med >= b_med
     dom_ms = f_med if dom_is_fwd else b_med
-    dom_bytes = fb if dom_is_fwd else bb
+    # without stored lists the backward call traces the rays again first
+    dom_bytes = fb if dom_is_fwd else (bb + fb if args.recompute else bb)
+    bwd_name = "k_trace (retrace) + k_backward" if args.recompute else "k_backward"
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     line = {
         "metric": "Mrays/s fwd+bwd @1M surfels (refit + forward + backward per step)" +
@@ -297,7 +299,7 @@ def run_c3(args):
         "build_ms": round(build_ms, 3),
         "hits_per_ray": round(H, 3),
         "bvh_depth": info["max_depth"],
-        "roofline": {"bound": "hbm", "kernel": "k_trace (forward)" if dom_is_fwd else "k_backward",
+        "roofline": {"bound": "hbm", "kernel": "k_trace (forward)" if dom_is_fwd else bwd_name,
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic() if dom_is_fwd and not sh else None,

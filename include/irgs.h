@@ -88,7 +88,7 @@ typedef struct {
 } irgs_params;
 
 #define IRGS_FLAG_BRUTE_FORCE 1u /* trace: test every surfel, no BVH */
-#define IRGS_FLAG_RECOMPUTE 2u   /* backward: re-march instead of reading saved hits */
+#define IRGS_FLAG_RECOMPUTE 2u   /* backward: trace again instead of reading saved hits */
 /* trace / backward: view-dependent colour (Sec. 3.1 models each surfel's
  * colour with spherical harmonics; the trace uses that colour, Sec. 3.3).
  * The F = 3 (deg + 1)^2 features of a surfel (deg <= 3: F = 3, 12, 27, 48)
@@ -212,7 +212,11 @@ irgs_status irgs_trace(irgs_scene scene, const irgs_params* params, int64_t R, c
  * gradients.  `saved` is the irgs_out of the forward call: n_hits is
  * required; with hit_ids and hit_T present (and IRGS_FLAG_RECOMPUTE unset)
  * rays with n_hits <= H_cap replay their saved hits, every other ray
- * re-marches its hits.  Parameters must not have changed since the forward
+ * re-marches its hits.  Without saved lists (or with IRGS_FLAG_RECOMPUTE)
+ * the call traces the rays again, in equal batches whose hit lists (256 per
+ * ray) fit a transient 4 GiB workspace, replays those lists and re-marches rays
+ * with more hits; results are the same either way up to the order of the
+ * gradient sums.  Parameters must not have changed since the forward
  * trace. */
 irgs_status irgs_trace_backward(irgs_scene scene, const irgs_params* params, int64_t R, const float* ro,
                                 const float* rd, const irgs_out* saved, const irgs_grad_in* grad_in,

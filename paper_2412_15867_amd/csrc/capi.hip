@@ -3,6 +3,7 @@
 // include/irgs.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -184,6 +185,10 @@ int ovf_slots_of(irgs_scene s)
 
 // Forward scratch: the ray-claim counter heads the deferred-list buffer.
 constexpr size_t kClaimBytes = 256;
+// Backward without stored hit lists: list capacity of the retrace and the
+// size its batches of lists (ids, T, O, D, n_hits, features) stay within.
+constexpr int kRetraceCap = 256;
+constexpr size_t kRetraceBytes = size_t(4) << 30;
 FlatScratch flat_scratch(void* ovf, int slots, void* dq)
 {
     FlatScratch f{};
@@ -507,19 +512,61 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
     if (R == 0 || s->n == 0) return IRGS_OK;
     const bool use_saved = !(p->flags & IRGS_FLAG_RECOMPUTE) && saved->hit_ids && saved->hit_T && saved->H_cap > 0;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const int slots = stack_need(s);  // the backward keeps its whole re-march stack in global memory
-    const size_t thr = static_cast<size_t>(trace_threads(R));
-    AsyncBuf ovf, ck;
-    hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
-    if (e == hipSuccess) e = ck.alloc(backward_scratch_words(R, s->n, s->F) * sizeof(float), hs);
-    if (e != hipSuccess) return hip_fail(e, "backward scratch");
+    const TraceParams tp = trace_params(p, s->F);
     RawSurfels raw{s->p.mu, s->p.quat, s->p.scale, s->p.opacity, s->p.feat};
     GradIn g{gin->g_opacity, gin->g_feat, gin->g_depth};
     GradOut go{grads->mu, grads->quat, grads->scale, grads->opacity, grads->feat};
-    OutPtrs sv = out_ptrs(saved);
-    e = launch_backward(view_of(s), raw, trace_params(p, s->F), p->k, R, ro, rd, sv, use_saved, g, go,
-                        static_cast<int*>(ovf.p), slots, static_cast<float*>(ck.p), hs);
-    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    const int slots = stack_need(s);  // the backward keeps its whole re-march stack in global memory
+    if (use_saved) {
+        const size_t thr = static_cast<size_t>(trace_threads(R));
+        AsyncBuf ovf, ck;
+        hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
+        if (e == hipSuccess) e = ck.alloc(backward_scratch_words(R, s->n, s->F) * sizeof(float), hs);
+        if (e != hipSuccess) return hip_fail(e, "backward scratch");
+        e = launch_backward(view_of(s), raw, tp, p->k, R, ro, rd, out_ptrs(saved), true, g, go,
+                            static_cast<int*>(ovf.p), slots, static_cast<float*>(ck.p), hs);
+        if (e != hipSuccess) return hip_fail(e, "backward launch");
+        return IRGS_OK;
+    }
+    // Without stored lists the rays are traced again, a batch at a time, into
+    // a transient list workspace, and the batch then takes the stored-list
+    // walk (the retrace composites exactly as the forward did, so its lists
+    // and T are the forward's); rays with more than kRetraceCap hits
+    // re-march.  The accumulated gradients add into `grads` per batch.
+    const int fo = tp.sh_deg >= 0 ? 3 : s->F;  // composited (and upstream) channels
+    const size_t per_ray = static_cast<size_t>(kRetraceCap) * 8 + (3 + fo) * sizeof(float);
+    const int64_t bmax = std::max<int64_t>(1, static_cast<int64_t>(kRetraceBytes / per_ray));
+    const int64_t nbatch = (R + bmax - 1) / bmax;
+    const int64_t B = (R + nbatch - 1) / nbatch;  // equal batches: no short last launch
+    const bool bvh = !(p->flags & IRGS_FLAG_BRUTE_FORCE);
+    const size_t thr = static_cast<size_t>(trace_threads(B));
+    AsyncBuf ovf, dq, ck, lists;
+    hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
+    if (e == hipSuccess && bvh) e = dq.alloc(kClaimBytes + thr * 2 * kDeferCap * sizeof(int), hs);
+    if (e == hipSuccess) e = ck.alloc(backward_scratch_words(B, s->n, s->F) * sizeof(float), hs);
+    if (e == hipSuccess) e = lists.alloc(static_cast<size_t>(B) * per_ray, hs);
+    if (e != hipSuccess) return hip_fail(e, "backward scratch");
+    OutPtrs tmp{};
+    tmp.hit_ids = static_cast<int32_t*>(lists.p);
+    tmp.hit_T = reinterpret_cast<float*>(tmp.hit_ids + static_cast<size_t>(B) * kRetraceCap);
+    tmp.O = tmp.hit_T + static_cast<size_t>(B) * kRetraceCap;
+    tmp.D = tmp.O + B;
+    tmp.n_hits = reinterpret_cast<int32_t*>(tmp.D + B);
+    tmp.feat = reinterpret_cast<float*>(tmp.n_hits + B);
+    tmp.H_cap = kRetraceCap;
+    const SceneView sv = view_of(s);
+    const FlatScratch fs = flat_scratch(ovf.p, bvh ? ovf_slots_of(s) : 0, dq.p);
+    for (int64_t b0 = 0; b0 < R; b0 += B) {
+        const int64_t nb = std::min(B, R - b0);
+        const float* bro = ro + 3 * b0;
+        const float* brd = rd + 3 * b0;
+        e = launch_trace(sv, tp, p->k, bvh, nb, bro, brd, tmp, fs, hs);
+        if (e != hipSuccess) return hip_fail(e, "backward retrace");
+        const GradIn gb{g.gO ? g.gO + b0 : nullptr, g.gF ? g.gF + b0 * fo : nullptr, g.gD ? g.gD + b0 : nullptr};
+        e = launch_backward(sv, raw, tp, p->k, nb, bro, brd, tmp, true, gb, go, static_cast<int*>(ovf.p), slots,
+                            static_cast<float*>(ck.p), hs);
+        if (e != hipSuccess) return hip_fail(e, "backward launch");
+    }
     return IRGS_OK;
 }
 

@@ -63,7 +63,7 @@ class TraceConfig:
     t_min: float = 0.0
     t_max: float = math.inf
     brute_force: bool = False
-    recompute: bool = False      # backward: re-march instead of storing hit lists
+    recompute: bool = False      # backward: trace the rays again instead of storing hit lists
     hit_cap: int = 64            # hits stored per ray for the backward (store mode)
     sh: bool = False             # features are RGB SH coefficients (view-dependent colour, 3 channels)
     normals: bool = False        # forward only: 3 more channels, the ray-facing normal (relighting)
@@ -271,8 +271,9 @@ class TraceFn(torch.autograd.Function):
     """Differentiable trace: (mu, quat, scale, opacity, feat, ro, rd) ->
     (opacity, feat, depth).  The scene must wrap the same parameter tensors
     and be built/refit for their current values.  Gradients flow to the five
-    surfel tensors (not to the rays).  ``cfg.recompute`` re-marches the hit
-    lists in the backward instead of storing them (less memory)."""
+    surfel tensors (not to the rays).  ``cfg.recompute`` traces the rays
+    again in the backward instead of storing their hit lists from the forward
+    (less memory held between the two)."""
 
     @staticmethod
     def forward(ctx, mu, quat, scale, opacity, feat, ro, rd, scene: Scene, cfg: Optional[TraceConfig] = None):

@@ -101,29 +101,53 @@ def test_small_hit_cap_falls_back_to_recompute(cube):
         np.testing.assert_allclose(a[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
 
 
-def test_many_rounds_past_the_checkpoints():
-    """k = 1 on 60 coaxial splats: 42 rounds, more than the 8 stored round
-    checkpoints, in re-march mode; closed-form and oracle gradients."""
-    n = 60
-    g = np.random.default_rng(30)
+def coaxial_splats(n, opacity, seed):
+    """n splats stacked along -z in a random order, two rays down the axis."""
+    g = np.random.default_rng(seed)
     perm = g.permutation(n)
     mu = np.stack([g.normal(0, 0.01, n), g.normal(0, 0.01, n), -0.05 * np.arange(n)], 1)[perm].astype(np.float32)
     q = np.tile(np.float32([1, 0, 0, 0]), (n, 1)) + g.normal(0, 0.05, (n, 4)).astype(np.float32)
     s = np.full((n, 2), 0.1, np.float32)
-    o = np.full(n, 0.2, np.float32)
+    o = np.full(n, opacity, np.float32)
     f = g.uniform(0, 1, (n, 3)).astype(np.float32)
     ro = np.float32([[0, 0, 1.0], [0.01, 0.02, 1.0]])
     rd = np.float32([[0, 0, -1.0], [0, 0, -1.0]])
     gO, gF, gD = np.float32([1, -0.5]), np.float32([[0.3, 0.2, 0.1], [1, 1, 1]]), np.float32([0.7, 0.1])
-    surf = (mu, q, s, o, f)
-    note("deep rays k=1 recompute")
-    fwd, a = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=64, recompute=True, k=1)
+    return (mu, q, s, o, f), ro, rd, gO, gF, gD
+
+
+def test_many_rounds_past_the_checkpoints():
+    """k = 1 on 60 coaxial splats: 42 rounds, more than the 8 stored round
+    checkpoints, re-marched (stored capacity 4); the same rays traced again
+    by the backward (no stored lists) and in store mode at k = 16."""
+    surf, ro, rd, gO, gF, gD = coaxial_splats(60, 0.2, 30)
+    note("deep rays k=1 re-march")
+    _, a = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=4, recompute=False, k=1)
+    note("deep rays k=1 retrace")
+    fwd, r = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=64, recompute=True, k=1)
     assert np.all(fwd["n_hits"] > 30)
     ref = ograd.grad_given_hits(surf, ro, rd, lists_of(fwd), gO, gF, gD)
     grad_close(a, ref)
+    grad_close(r, ref)
     _, b = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=64, recompute=False, k=16)
     for name, _ in NAMES:
         np.testing.assert_allclose(a[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
+        np.testing.assert_allclose(r[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
+
+
+def test_retrace_longer_than_its_list_capacity():
+    """300 faint coaxial splats: every hit composites (T stays above T_min),
+    more hits than the 256 the backward's retrace keeps per ray, so those
+    rays re-march; oracle gradients and store mode agree."""
+    surf, ro, rd, gO, gF, gD = coaxial_splats(300, 0.01, 33)
+    note("300-hit rays retrace")
+    fwd, r = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=512, recompute=True, k=16)
+    assert np.all(fwd["n_hits"] > 256)
+    ref = ograd.grad_given_hits(surf, ro, rd, lists_of(fwd), gO, gF, gD)
+    grad_close(r, ref)
+    _, b = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=512, recompute=False, k=16)
+    for name, _ in NAMES:
+        np.testing.assert_allclose(r[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
 
 
 def test_finite_differences_on_surface_patch():
@@ -197,7 +221,9 @@ def test_full_size_headline_config_sampled():
     """The benchmarked configuration at full size -- 1M surfels, 256x256x64 =
     4,194,304 MC rays, k = 16, one launch each way -- with the forward
     validated on 384 sampled rays and the backward checked against the FP64
-    oracle with upstream gradients non-zero only on 2,048 sampled rays."""
+    oracle with upstream gradients non-zero only on 2,048 sampled rays; the
+    backward also without stored lists (the rays traced again in three
+    equal batches)."""
     from paper_2412_15867_amd import TraceConfig, trace, trace_backward
     lay = synth.layout()
     sc = synth.surface_scene(1_000_000, F=8, lay=lay)
@@ -209,9 +235,13 @@ def test_full_size_headline_config_sampled():
     cfg = TraceConfig(k=16)
     res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=256)
     grads = trace_backward(scene, dev(ro), dev(rd), res, dev(gO), dev(gF), dev(gD), cfg=cfg)
+    note("full size backward, rays traced again")
+    grads_re = trace_backward(scene, dev(ro), dev(rd), res, dev(gO), dev(gF), dev(gD),
+                              cfg=TraceConfig(k=16, recompute=True))
     torch.cuda.synchronize()
     fwd = to_np(res)
     g = {k: v.cpu().numpy().astype(np.float64) for k, v in grads.items()}
+    g_re = {k: v.cpu().numpy().astype(np.float64) for k, v in grads_re.items()}
     scene.close()
     assert fwd["n_hits"].max() <= 256
     sample = np.sort(np.random.default_rng(50).choice(R, 384, replace=False))
@@ -223,12 +253,13 @@ def test_full_size_headline_config_sampled():
     lists = lists[:, :max(1, int(fwd["n_hits"][idx].max()))]
     ref = ograd.grad_given_hits(sc.astuple(), ro[idx], rd[idx], lists, gO[idx], gF[idx], gD[idx])
     touched = np.unique(lists[lists >= 0])
-    for name, key in NAMES:
-        a = g[name].reshape(g[name].shape[0], -1)
-        b = ref[key].reshape(ref[key].shape[0], -1)
-        untouched = np.setdiff1d(np.arange(a.shape[0]), touched)
-        assert np.all(a[untouched[:100000]] == 0), name
-        a, b = a[touched], b[touched]
-        floor = np.abs(b).mean() + 1e-30
-        err = np.abs(a - b) / (np.abs(b) + floor)
-        assert err.max() <= 1e-3, (name, err.max())
+    for gg in (g, g_re):
+        for name, key in NAMES:
+            a = gg[name].reshape(gg[name].shape[0], -1)
+            b = ref[key].reshape(ref[key].shape[0], -1)
+            untouched = np.setdiff1d(np.arange(a.shape[0]), touched)
+            assert np.all(a[untouched[:100000]] == 0), name
+            a, b = a[touched], b[touched]
+            floor = np.abs(b).mean() + 1e-30
+            err = np.abs(a - b) / (np.abs(b) + floor)
+            assert err.max() <= 1e-3, (name, err.max())
