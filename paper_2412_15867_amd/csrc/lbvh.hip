@@ -391,17 +391,48 @@ __global__ void k_node_depth(int nint, const BvhNode* __restrict__ nodes, int* _
     atomicMax(maxd, d);
 }
 
-__global__ void k_level_hist(int nint, const int* __restrict__ ndepth, int* __restrict__ hist)
+// Nodes per depth.  Trees of at most kLevelBins levels count in LDS first
+// (one global add per block and level instead of one per node: all nodes
+// fall into a few dozen bins, whose global atomics would serialise).
+constexpr int kLevelBins = 1024;
+
+__global__ void k_level_hist(int nint, int nbins, const int* __restrict__ ndepth, int* __restrict__ hist)
 {
+    __shared__ int h[kLevelBins];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < nint) atomicAdd(&hist[ndepth[x]], 1);
+    if (nbins > kLevelBins) {
+        if (x < nint) atomicAdd(&hist[ndepth[x]], 1);
+        return;
+    }
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    if (x < nint) atomicAdd(&h[ndepth[x]], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        if (h[i] > 0) atomicAdd(&hist[i], h[i]);
 }
 
-__global__ void k_level_scatter(int nint, const int* __restrict__ ndepth, int* __restrict__ cursor,
+// Node ids grouped by depth: `cursor` starts at each level's offset.  Within
+// a level the order is arbitrary (the refit of a level is order-free).
+__global__ void k_level_scatter(int nint, int nbins, const int* __restrict__ ndepth, int* __restrict__ cursor,
                                 int* __restrict__ level_nodes)
 {
+    __shared__ int h[kLevelBins];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < nint) level_nodes[atomicAdd(&cursor[ndepth[x]], 1)] = x;
+    if (nbins > kLevelBins) {
+        if (x < nint) level_nodes[atomicAdd(&cursor[ndepth[x]], 1)] = x;
+        return;
+    }
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int d = x < nint ? ndepth[x] : 0;
+    const int rank = x < nint ? atomicAdd(&h[d], 1) : 0;
+    __syncthreads();
+    // each level's block count becomes the block's base slot in that level
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+        if (h[i] > 0) h[i] = atomicAdd(&cursor[i], h[i]);
+    __syncthreads();
+    if (x < nint) level_nodes[h[d] + rank] = x;
 }
 
 // Box b into slot `which` of node nd: six scalar stores, so that the two
@@ -923,7 +954,7 @@ static hipError_t group_levels(BuildArgs& a, void* scratch, hipStream_t st)
     int* hist = maxd + 1;
     e = fill_u32(hist, D + 1, 0u, st);
     if (e != hipSuccess) return e;
-    k_level_hist<<<blocks_for(nint, 256), 256, 0, st>>>(nint, ndepth, hist);
+    k_level_hist<<<blocks_for(nint, 256), 256, 0, st>>>(nint, D + 1, ndepth, hist);
     std::vector<int> h(D + 1);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h.data(), hist, sizeof(int) * (D + 1), hipMemcpyDeviceToHost, st);
@@ -934,7 +965,7 @@ static hipError_t group_levels(BuildArgs& a, void* scratch, hipStream_t st)
     for (int d = 0; d <= D; ++d) off[d + 1] = off[d] + h[d];
     e = hipMemcpyAsync(hist, off.data(), sizeof(int) * (D + 1), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    k_level_scatter<<<blocks_for(nint, 256), 256, 0, st>>>(nint, ndepth, hist, a.level_nodes);
+    k_level_scatter<<<blocks_for(nint, 256), 256, 0, st>>>(nint, D + 1, ndepth, hist, a.level_nodes);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host offsets outlive this call
     return e;
