@@ -687,7 +687,7 @@ def main():
     ap.add_argument("--points", type=int, default=256 * 256)
     ap.add_argument("--dirs", type=int, default=64)
     ap.add_argument("--k", type=int, default=None,
-                    help="k-buffer size (default 16; c5: 64; pbr / relight: 64 up to 2^19 rays, else 32)")
+                    help="k-buffer size (default 16; c5: 64; serve: 32; pbr / relight: 64 up to 2^19 rays, else 32)")
     ap.add_argument("--no-k32", action="store_true", help="default workload: skip the same step timed at k = 32")
     ap.add_argument("--leaf-size", type=int, default=0, help="surfels per leaf cluster (0: the library default)")
     ap.add_argument("--builder", default="ploc", choices=["ploc", "radix"],
@@ -706,6 +706,8 @@ def main():
             args.k = 64 if args.pixels * 256 <= (1 << 19) else 32  # tail-bound launches: fewer rounds
         elif args.workload == "c5":
             args.k = 64  # 5M surfels: past the Infinity Cache every round's re-traversal costs HBM latency
+        elif args.workload == "serve":
+            args.k = 32  # scenes up to 3M surfels (packed launches take 16 or 32)
         else:
             args.k = 16  # the paper's k
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
