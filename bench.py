@@ -191,7 +191,7 @@ def run_c3(args):
     build_ms = (time.perf_counter() - b0) * 1e3
     scene.set_params(*params)
     info = scene.info()
-    cfg = TraceConfig(k=args.k, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh)
+    cfg = TraceConfig(k=args.k, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh, sort_rays=args.sort_rays)
     log(f"built LBVH in {build_ms:.1f} ms, depth {info['max_depth']}; cfg {cfg}")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -288,7 +288,8 @@ def run_c3(args):
         "config": {"workload": f"{N} surfels (8 spheres + 4 planes, F={F}"
                                f"{f' = RGB SH degree {args.sh_deg}' if sh else ''}), {args.points}x{args.dirs} "
                                f"cosine MC rays = {R}, refit+fwd+bwd, k={args.k}, T_min=1e-4, "
-                               f"{'recompute' if args.recompute else 'store'} mode, {args.builder} tree",
+                               f"{'recompute' if args.recompute else 'store'} mode, {args.builder} tree"
+                               f"{', rays sorted by origin' if args.sort_rays else ''}",
                    "surfels": N, "rays": R, "features": F, "k": args.k, "tree": args.builder},
         "fwd_mrays_s": round(R / (fwd_only_ms * 1e-3) / 1e6, 3),
         **({"k32": alt} if alt else {}),
@@ -474,7 +475,7 @@ def run_c5(args):
     scene = Scene(*params, builder=args.builder, leaf_size=args.leaf_size)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - b0) * 1e3
-    cfg = TraceConfig(k=args.k, recompute=args.recompute)
+    cfg = TraceConfig(k=args.k, recompute=args.recompute, sort_rays=args.sort_rays)
     hit_cap = 0 if args.recompute else 128
     ev = lambda: torch.cuda.Event(enable_timing=True)
     phases = []
@@ -510,7 +511,8 @@ def run_c5(args):
             "warmup": args.warmup, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"5000000 surfels, 1024x1024x32 = {R} MC rays, F=8, k={args.k}, "
-                                   f"{'recompute' if args.recompute else 'store'} mode"},
+                                   f"{'recompute' if args.recompute else 'store'} mode"
+                                   f"{', rays sorted by origin' if args.sort_rays else ''}"},
             "fwd_ms": round(float(np.median(f)), 3), "bwd_ms": round(float(np.median(b)), 3),
             "refit_ms": round(float(np.median(u)), 3), "build_ms": round(build_ms, 3)}
     scene.close()
@@ -694,6 +696,10 @@ def main():
                     help="binary tree under the 4-wide BVH: PLOC clustering or the Morton radix tree")
     ap.add_argument("--hit-cap", type=int, default=256)
     ap.add_argument("--recompute", action="store_true")
+    ap.add_argument("--sort-rays", dest="sort_rays", action="store_true", default=None,
+                    help="default and c5 workloads: trace rays in the Morton order of their origins "
+                         "(default: on for c5, whose scene outgrows the caches)")
+    ap.add_argument("--no-sort-rays", dest="sort_rays", action="store_false")
     ap.add_argument("--sh-deg", type=int, default=-1,
                     help="default workload with view-dependent colour: RGB SH coefficients of this degree (0..3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -710,6 +716,8 @@ def main():
             args.k = 32  # scenes up to 3M surfels (packed launches take 16 or 32)
         else:
             args.k = 16  # the paper's k
+    if args.sort_rays is None:
+        args.sort_rays = args.workload == "c5"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the trace shards rays across GPUs with no exchange in the "
               "forward and one gradient all-reduce in the backward, which this single-GPU build does not "

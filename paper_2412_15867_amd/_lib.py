@@ -24,6 +24,7 @@ FLAG_RECOMPUTE = 2
 FLAG_SH = 4          # features are RGB SH coefficients; 3 composited channels
 FLAG_NORMAL = 8      # 3 more composited channels: the ray-facing normal (forward only)
 FLAG_RADIX_TREE = 16  # scene build: Morton radix tree instead of PLOC clustering
+FLAG_SORT_RAYS = 32  # trace rays in the Morton order of their origins (same results)
 
 
 class Surfels(ctypes.Structure):

@@ -382,11 +382,17 @@ size_t irgs_scene_bytes(int64_t n, int32_t F)
 
 size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
 {
-    (void)F;
     if (R <= 0) return 0;
     const size_t thr = static_cast<size_t>(trace_threads(R));
     size_t b = thr * (64 + 2 * kDeferCap) * sizeof(int) + kClaimBytes;  // stack overflow, deferred lists
-    if (flags & IRGS_FLAG_RECOMPUTE) b += thr * kBwdCheckpoints * 4 * sizeof(float);
+    if (flags & IRGS_FLAG_SORT_RAYS) b += ray_sort_words(R) * sizeof(float);
+    if (flags & IRGS_FLAG_RECOMPUTE) {  // the backward's retrace: one batch of lists, its checkpoints
+        const int fo = (flags & IRGS_FLAG_SH) ? 3 : F;
+        const size_t per_ray = static_cast<size_t>(kRetraceCap) * 8 + (3 + fo) * sizeof(float);
+        const int64_t bmax = std::max<int64_t>(1, static_cast<int64_t>(kRetraceBytes / per_ray));
+        const int64_t nb = (R + bmax - 1) / bmax;
+        b += static_cast<size_t>((R + nb - 1) / nb) * per_ray + thr * kBwdCheckpoints * 4 * sizeof(float);
+    }
     return b;  // plus, for a backward, 4 * ceil32(10 + F) bytes per surfel
 }
 
@@ -490,13 +496,20 @@ irgs_status irgs_trace(irgs_scene s, const irgs_params* p, int64_t R, const floa
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const bool bvh = !(p->flags & IRGS_FLAG_BRUTE_FORCE);
     const int slots = bvh ? ovf_slots_of(s) : 0;
-    AsyncBuf ovf, dq;
+    const bool sorted = bvh && (p->flags & IRGS_FLAG_SORT_RAYS) && ray_sort_words(R) > 0;
+    AsyncBuf ovf, dq, srt;
     const size_t thr = static_cast<size_t>(trace_threads(R));
     hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
     if (e == hipSuccess && bvh) e = dq.alloc(kClaimBytes + thr * 2 * kDeferCap * sizeof(int), hs);
+    if (e == hipSuccess && sorted) e = srt.alloc(ray_sort_words(R) * sizeof(float), hs);
     if (e != hipSuccess) return hip_fail(e, "trace scratch");
-    e = launch_trace(view_of(s), trace_params(p, s->F), p->k, bvh, R, ro, rd, out_ptrs(out),
-                     flat_scratch(ovf.p, slots, dq.p), hs);
+    const SceneView sv = view_of(s);
+    FlatScratch fs = flat_scratch(ovf.p, slots, dq.p);
+    if (sorted) {
+        e = ray_order_by_origin(sv, R, ro, srt.p, &fs.order, hs);
+        if (e != hipSuccess) return hip_fail(e, "ray order");
+    }
+    e = launch_trace(sv, trace_params(p, s->F), p->k, bvh, R, ro, rd, out_ptrs(out), fs, hs);
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return IRGS_OK;
 }
@@ -540,9 +553,11 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
     const int64_t B = (R + nbatch - 1) / nbatch;  // equal batches: no short last launch
     const bool bvh = !(p->flags & IRGS_FLAG_BRUTE_FORCE);
     const size_t thr = static_cast<size_t>(trace_threads(B));
-    AsyncBuf ovf, dq, ck, lists;
+    const bool sorted = bvh && (p->flags & IRGS_FLAG_SORT_RAYS) && ray_sort_words(B) > 0;
+    AsyncBuf ovf, dq, ck, lists, srt;
     hipError_t e = ovf.alloc(thr * slots * sizeof(int), hs);
     if (e == hipSuccess && bvh) e = dq.alloc(kClaimBytes + thr * 2 * kDeferCap * sizeof(int), hs);
+    if (e == hipSuccess && sorted) e = srt.alloc(ray_sort_words(B) * sizeof(float), hs);
     if (e == hipSuccess) e = ck.alloc(backward_scratch_words(B, s->n, s->F) * sizeof(float), hs);
     if (e == hipSuccess) e = lists.alloc(static_cast<size_t>(B) * per_ray, hs);
     if (e != hipSuccess) return hip_fail(e, "backward scratch");
@@ -555,11 +570,15 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
     tmp.feat = reinterpret_cast<float*>(tmp.n_hits + B);
     tmp.H_cap = kRetraceCap;
     const SceneView sv = view_of(s);
-    const FlatScratch fs = flat_scratch(ovf.p, bvh ? ovf_slots_of(s) : 0, dq.p);
+    FlatScratch fs = flat_scratch(ovf.p, bvh ? ovf_slots_of(s) : 0, dq.p);
     for (int64_t b0 = 0; b0 < R; b0 += B) {
         const int64_t nb = std::min(B, R - b0);
         const float* bro = ro + 3 * b0;
         const float* brd = rd + 3 * b0;
+        if (sorted) {
+            e = ray_order_by_origin(sv, nb, bro, srt.p, &fs.order, hs);
+            if (e != hipSuccess) return hip_fail(e, "ray order");
+        }
         e = launch_trace(sv, tp, p->k, bvh, nb, bro, brd, tmp, fs, hs);
         if (e != hipSuccess) return hip_fail(e, "backward retrace");
         const GradIn gb{g.gO ? g.gO + b0 : nullptr, g.gF ? g.gF + b0 * fo : nullptr, g.gD ? g.gD + b0 : nullptr};

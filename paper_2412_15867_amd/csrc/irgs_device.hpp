@@ -175,6 +175,44 @@ __device__ __forceinline__ int key_pos(uint64_t k) { return static_cast<int>(sta
 
 constexpr uint64_t kKeyNone = ~0ull;  // larger than every key
 
+// The root node's box: the union of its non-empty child slots (lo > hi
+// when the scene is empty).
+__device__ __forceinline__ void root_box(const WideNode* __restrict__ root, float lo[3], float hi[3])
+{
+    const float inf = __int_as_float(0x7f800000);
+    const float* w = reinterpret_cast<const float*>(root);  // lo_x[4], lo_y[4], lo_z[4], hi_x[4], hi_y[4], hi_z[4]
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = inf;
+        hi[a] = -inf;
+    }
+    for (int c = 0; c < 4; ++c) {
+        if (w[c] == inf) continue;  // empty slot
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], w[4 * a + c]);
+            hi[a] = fmaxf(hi[a], w[12 + 4 * a + c]);
+        }
+    }
+}
+
+// 30-bit Morton code (10 bits per axis) of point x in the box [lo, hi],
+// clamped to the box.
+__device__ __forceinline__ uint32_t morton30(const float x[3], const float lo[3], const float hi[3])
+{
+    uint32_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+        const float ext = hi[a] - lo[a];
+        const float u = ext > 0.0f ? (x[a] - lo[a]) / ext : 0.0f;
+        const uint32_t q = static_cast<uint32_t>(fminf(fmaxf(u * 1024.0f, 0.0f), 1023.0f));
+        uint32_t v = q;  // spread 10 bits to every third position
+        v = (v | (v << 16)) & 0x030000ffu;
+        v = (v | (v << 8)) & 0x0300f00fu;
+        v = (v | (v << 4)) & 0x030c30c3u;
+        v = (v | (v << 2)) & 0x09249249u;
+        code |= v << (2 - a);
+    }
+    return code;
+}
+
 // Slab tests take the ray as (inverse direction i, no = -o * i) so that each
 // slab distance is one fma: (l - o) / d == l * i + no.  The fused form
 // rounds differently from (l - o) * i by less than an ulp of o * i, far

@@ -113,7 +113,14 @@ struct FlatScratch {
     int ovf_slots;
     int* dbuf;                     // deferred-work lists: 2 * kDeferCap ints per thread (BVH launches)
     unsigned long long* next_ray;  // ray-claim counter (BVH launches); the launch zeroes it
+    const uint32_t* order;         // optional claim order (slot -> ray), BVH launches over one scene
 };
+
+// Claim order of a forward trace: rays sorted by the Morton code of their
+// origin in the scene's root box.  `buf` holds ray_sort_words(R) floats;
+// *order points into it afterwards.  Needs R <= 2^31 - 1 and a built scene.
+hipError_t ray_order_by_origin(const SceneView& sc, int64_t R, const float* ro, void* buf, const uint32_t** order,
+                               hipStream_t st);
 
 // Forward trace.  use_bvh = false tests every record (the plain tracer).
 hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,

@@ -467,34 +467,15 @@ __global__ void k_ray_keys(int64_t R, const float* __restrict__ ro, const float*
 {
     const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     if (r >= R) return;
-    const float inf = __int_as_float(0x7f800000);
-    const float* w = reinterpret_cast<const float*>(root);  // lo_x[4], lo_y[4], lo_z[4], hi_x[4], hi_y[4], hi_z[4]
-    float lo[3] = {inf, inf, inf}, hi[3] = {-inf, -inf, -inf};
-    for (int c = 0; c < 4; ++c) {
-        if (w[c] == inf) continue;  // empty slot
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fminf(lo[a], w[4 * a + c]);
-            hi[a] = fmaxf(hi[a], w[12 + 4 * a + c]);
-        }
-    }
+    float lo[3], hi[3];
+    root_box(root, lo, hi);
     uint64_t key = 0xffffffffull;
     const float o = O[r];
     if (o > 0.0f && lo[0] <= hi[0]) {
         const float t = D[r] / o;
-        uint32_t code = 0;
-        for (int a = 0; a < 3; ++a) {
-            const float x = fmaf(t, rd[3 * r + a], ro[3 * r + a]);
-            const float ext = hi[a] - lo[a];
-            const float u = ext > 0.0f ? (x - lo[a]) / ext : 0.0f;
-            const uint32_t q = static_cast<uint32_t>(fminf(fmaxf(u * 1024.0f, 0.0f), 1023.0f));
-            uint32_t v = q;  // spread 10 bits to every third position
-            v = (v | (v << 16)) & 0x030000ffu;
-            v = (v | (v << 8)) & 0x0300f00fu;
-            v = (v | (v << 4)) & 0x030c30c3u;
-            v = (v | (v << 2)) & 0x09249249u;
-            code |= v << (2 - a);
-        }
-        key = code;
+        const float x[3] = {fmaf(t, rd[3 * r], ro[3 * r]), fmaf(t, rd[3 * r + 1], ro[3 * r + 1]),
+                            fmaf(t, rd[3 * r + 2], ro[3 * r + 2])};
+        key = morton30(x, lo, hi);
     }
     keys[r] = key;
     vals[r] = static_cast<uint32_t>(r);

@@ -33,17 +33,19 @@ struct LaneRay {
     SceneView sc;  // the item's scene (packed launches only)
 };
 
-// One scene, rays [0, R).
+// One scene, rays [0, R), claimed in `order` when given.
 struct PlainSource {
     SceneView sc;
     OutPtrs o;
     const float* ro;
     const float* rd;
     int64_t R;
+    const uint32_t* order;
 
     __device__ __forceinline__ bool load(int64_t slot, LaneRay& lr, Ray& ray) const
     {
         if (slot >= R) return false;
+        if (order) slot = order[slot];
         lr.r = slot;
         lr.item = 0;
         ray = load_ray(ro, rd, slot);

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 
     Stack st{as_lds(lds_stack), as_glb(fs.ovf_slots > 0 ? fs.ovf + gtid : nullptr), static_cast<int>(nthr),
              static_cast<int>(threadIdx.x), 0, kStackLds};
     if (BVH) {
-        const PlainSource src{sc, out, ro, rd, R};
+        const PlainSource src{sc, out, ro, rd, R, fs.order};
         Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
         trace_flat<K, FM, CM>(src, fs.next_ray, P, st, dq);
     } else {
@@ -202,6 +202,41 @@ hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev,
     if (k == 32 && P.F <= 64)
         return launch_packed_kf<32, 64>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
     return hipErrorInvalidValue;
+}
+
+namespace {
+
+// Sort key of a ray for the forward's claim order: the Morton code of its
+// origin in the root's box (origins outside it clamp to its faces).
+__global__ void k_origin_keys(int64_t R, const float* __restrict__ ro, const WideNode* __restrict__ root,
+                              uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (r >= R) return;
+    float lo[3], hi[3];
+    root_box(root, lo, hi);
+    const float x[3] = {ro[3 * r], ro[3 * r + 1], ro[3 * r + 2]};
+    keys[r] = lo[0] <= hi[0] ? morton30(x, lo, hi) : 0u;  // NaN coordinates clamp to a face
+    vals[r] = static_cast<uint32_t>(r);
+}
+
+}  // namespace
+
+hipError_t ray_order_by_origin(const SceneView& sc, int64_t R, const float* ro, void* buf, const uint32_t** order,
+                               hipStream_t st)
+{
+    *order = nullptr;
+    if (R <= 1 || R > 0x7fffffffLL || sc.n <= 0) return hipSuccess;
+    uint64_t* k0 = static_cast<uint64_t*>(buf);
+    uint64_t* k1 = k0 + R;
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(k1 + R);
+    uint32_t* v1 = v0 + R;
+    uint32_t* counts = v1 + R;
+    k_origin_keys<<<static_cast<unsigned>((R + 255) / 256), 256, 0, st>>>(R, ro, sc.wnodes, k0, v0);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = sort_pairs(static_cast<int>(R), k0, v0, k1, v1, counts, 4, st);
+    if (e == hipSuccess) *order = v0;
+    return e;
 }
 
 hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool use_bvh, int64_t R,

@@ -56,8 +56,11 @@ def _req(t: torch.Tensor, name: str, shape, dtype=torch.float32, device=None) ->
 class TraceConfig:
     """Trace parameters (see irgs_params in include/irgs.h).  ``k`` (the
     k-buffer size of Sec. 3.2, the paper's 16) changes only the number of
-    marching rounds, never the result; on gfx950 k = 32 runs faster on every
-    workload measured (fewer rounds outweigh the lower occupancy)."""
+    marching rounds, never the result; on gfx950 k = 32 runs as fast or
+    faster on every workload measured, and k = 64 faster still for launches
+    bound by their slowest rays and for scenes past the caches (fewer rounds
+    outweigh the lower occupancy).  ``sort_rays`` hands rays to the traversal
+    in the Morton order of their origins (results unchanged bit for bit)."""
     k: int = 16
     T_min: float = DEFAULT_T_MIN
     t_min: float = 0.0
@@ -67,9 +70,11 @@ class TraceConfig:
     hit_cap: int = 64            # hits stored per ray for the backward (store mode)
     sh: bool = False             # features are RGB SH coefficients (view-dependent colour, 3 channels)
     normals: bool = False        # forward only: 3 more channels, the ray-facing normal (relighting)
+    sort_rays: bool = False      # trace rays in the Morton order of their origins (same results)
 
     def flags(self) -> int:
-        return (_lib.FLAG_SH if self.sh else 0) | (_lib.FLAG_NORMAL if self.normals else 0)
+        return ((_lib.FLAG_SH if self.sh else 0) | (_lib.FLAG_NORMAL if self.normals else 0) |
+                (_lib.FLAG_SORT_RAYS if self.sort_rays else 0))
 
     def out_channels(self, F: int) -> int:
         """Composited feature channels for a scene with F features."""

@@ -42,6 +42,29 @@ def test_every_declared_symbol_is_exported(L):
     assert set(_lib.SIGNATURES) == set(names)
 
 
+def test_binding_flags_match_the_header():
+    """Every IRGS_FLAG_* of include/irgs.h has the same value in the binding."""
+    from paper_2412_15867_amd import _lib
+    flags = dict(re.findall(r"#define IRGS_FLAG_([A-Z_]+)\s+(\d+)u", open(HEADER).read()))
+    assert len(flags) >= 6
+    for name, value in flags.items():
+        assert getattr(_lib, "FLAG_" + name) == int(value), name
+
+
+def test_trace_bytes_count_the_optional_scratch(L):
+    """The per-call scratch grows with the ray sort (24 B per ray and more)
+    and, for the backward that traces again, with one batch of hit lists."""
+    from paper_2412_15867_amd import _lib
+    L.irgs_trace_bytes.restype = ctypes.c_size_t
+    L.irgs_trace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32]
+    R = 1 << 20
+    base = L.irgs_trace_bytes(R, 8, 0)
+    assert L.irgs_trace_bytes(R, 8, _lib.FLAG_SORT_RAYS) >= base + 24 * R
+    assert L.irgs_trace_bytes(R, 8, _lib.FLAG_RECOMPUTE) >= base + R * 256 * 8
+    assert L.irgs_trace_bytes(1 << 26, 8, _lib.FLAG_RECOMPUTE) < (5 << 30) + L.irgs_trace_bytes(1 << 26, 8, 0)
+    assert L.irgs_trace_bytes(0, 8, _lib.FLAG_SORT_RAYS) == 0
+
+
 def test_status_strings_and_version(L):
     assert L.irgs_status_str(0) == b"ok"
     assert L.irgs_status_str(-1) == b"invalid argument"

@@ -31,10 +31,10 @@ def grad_close(g_gpu, g_ref, rel=1e-3):
     return worst
 
 
-def gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=256, recompute=False, k=16, T_min=1e-4):
+def gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=256, recompute=False, k=16, T_min=1e-4, sort_rays=False):
     from paper_2412_15867_amd import TraceConfig, trace, trace_backward
     scene = make_scene(surf)
-    cfg = TraceConfig(k=k, T_min=T_min, recompute=recompute)
+    cfg = TraceConfig(k=k, T_min=T_min, recompute=recompute, sort_rays=sort_rays)
     res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=hit_cap)
     grads = trace_backward(scene, dev(ro), dev(rd), res, dev(gO), dev(gF), dev(gD), cfg=cfg)
     torch.cuda.synchronize()
@@ -81,11 +81,14 @@ def test_wide_features_match_fp64_oracle(F):
     grad_close(g, ref)
 
 
-def test_recompute_equals_store(cube):
+@pytest.mark.parametrize("sort_rays", [False, True])
+def test_recompute_equals_store(cube, sort_rays):
+    """The backward without stored lists (rays traced again, optionally in
+    the Morton order of their origins) gives the store mode's gradients."""
     sc, ro, rd, gO, gF, gD = cube
-    note("cube backward recompute")
+    note(f"cube backward recompute, sort_rays={sort_rays}")
     _, a = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD)
-    _, b = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD, hit_cap=0, recompute=True)
+    _, b = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD, hit_cap=0, recompute=True, sort_rays=sort_rays)
     for name, _ in NAMES:
         np.testing.assert_allclose(a[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(a[name]).max())
 

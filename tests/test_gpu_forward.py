@@ -287,6 +287,32 @@ def test_surface_200k_full_launch_sampled(surface200k):
     assert 0.05 < frac_hit < 1.0
 
 
+@pytest.mark.parametrize("k", [16, 64])
+def test_sorted_rays_change_nothing(surface200k, k):
+    """Rays handed to the traversal in the Morton order of their origins: the
+    outputs, in the caller's order, equal the unsorted trace bit for bit
+    (ragged count, a few invalid rays among them)."""
+    from paper_2412_15867_amd import trace
+    sc, ro_all, rd_all = surface200k
+    R = 100_003
+    ro, rd = ro_all[:R].copy(), rd_all[:R].copy()
+    ro[7] = np.nan
+    rd[11] = 0.0
+    ro[13] = (50.0, -50.0, 50.0)  # origin outside the scene box
+    note(f"sorted vs unsorted rays, k={k}")
+    scene = make_scene(sc)
+    a = to_np(trace(scene, dev(ro), dev(rd), hit_cap=256, k=k))
+    b = to_np(trace(scene, dev(ro), dev(rd), hit_cap=256, k=k, sort_rays=True))
+    torch.cuda.synchronize()
+    scene.close()
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(a[key], b[key]), key
+    m = np.arange(256)[None, :] < a["n_hits"][:, None]
+    assert np.array_equal(np.where(m, a["hit_ids"], -1), np.where(m, b["hit_ids"], -1))
+    assert np.array_equal(np.where(m, a["hit_T"], 0), np.where(m, b["hit_T"], 0))
+    assert a["n_hits"][7] == 0 and a["n_hits"][11] == 0 and a["T"][7] == 1.0
+
+
 @pytest.mark.parametrize("builder", ["ploc", "radix"])
 def test_refit_equals_brute_force_and_rebuild(surface200k, builder):
     """Two training-like updates in place (centres += N(0, 1e-3), scales *=
