@@ -476,7 +476,7 @@ def run_c5(args):
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - b0) * 1e3
     cfg = TraceConfig(k=args.k, recompute=args.recompute, sort_rays=args.sort_rays)
-    hit_cap = 0 if args.recompute else 128
+    hit_cap = 0 if args.recompute else args.hit_cap
     ev = lambda: torch.cuda.Event(enable_timing=True)
     phases = []
     steps = args.steps

@@ -67,7 +67,11 @@ class TraceConfig:
     t_max: float = math.inf
     brute_force: bool = False
     recompute: bool = False      # backward: trace the rays again instead of storing hit lists
-    hit_cap: int = 64            # hits stored per ray for the backward (store mode)
+    # hits stored per ray for the backward (store mode, 8 bytes each); rays
+    # with more re-march in the backward, about ten times a forward per ray,
+    # so the capacity should cover nearly every ray (256 covers the 1M-surfel
+    # Monte Carlo workload: at 64 its backward takes 696 ms instead of 24.5)
+    hit_cap: int = 256
     sh: bool = False             # features are RGB SH coefficients (view-dependent colour, 3 channels)
     normals: bool = False        # forward only: 3 more channels, the ray-facing normal (relighting)
     sort_rays: bool = False      # trace rays in the Morton order of their origins (same results)
