@@ -229,7 +229,7 @@ def run_c3(args):
     alt = None
     if args.k == 16 and not args.no_k32:
         cfg_main = cfg
-        cfg = TraceConfig(k=32, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh)
+        cfg = TraceConfig(k=32, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh, sort_rays=args.sort_rays)
         step(False)
         torch.cuda.synchronize()
         ev32 = []
