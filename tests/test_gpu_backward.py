@@ -67,16 +67,17 @@ def test_cube_gradients_match_fp64_oracle(cube):
     note(f"cube worst rel err {w}")
 
 
+@pytest.mark.parametrize("recompute", [False, True])
 @pytest.mark.parametrize("F", [12, 40])
-def test_wide_features_match_fp64_oracle(F):
+def test_wide_features_match_fp64_oracle(F, recompute):
     """More features than the backward pre-reduces in LDS (F > 8): those
     launches take rays in the order of where they land; the sums are the
-    same."""
+    same, with stored lists and with the rays traced again."""
     sc = synth.cube_scene(F=F)
     ro, rd = synth.pinhole_rays(32, 32)
     gO, gF, gD, _ = synth.upstream(ro.shape[0], F)
-    note(f"cube backward F={F}")
-    fwd, g = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD)
+    note(f"cube backward F={F} recompute={recompute}")
+    fwd, g = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD, recompute=recompute)
     ref = ograd.grad_given_hits(sc.astuple(), ro, rd, lists_of(fwd), gO, gF, gD)
     grad_close(g, ref)
 
