@@ -123,7 +123,8 @@ typedef struct {
  * caches and the caller's rays are spatially incoherent (5M surfels, random
  * surface points: forward -11% at k = 64).  Extra scratch: 24 bytes per ray
  * plus the sort's tile counts (irgs_trace_bytes).  Ignored by
- * irgs_trace_packed. */
+ * irgs_trace_packed, by brute-force traces and by calls of more than
+ * 2^31 - 1 rays (traced in the caller's order). */
 #define IRGS_FLAG_SORT_RAYS 32u
 
 /* Outputs of a trace, caller-allocated (R = number of rays):
