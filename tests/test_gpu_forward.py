@@ -123,6 +123,32 @@ def test_k_does_not_change_the_result(c1, k):
         assert np.array_equal(a[key], b[key]), (k, key)
 
 
+@pytest.mark.parametrize("k", [4, 16])
+def test_work_counters(c1, k):
+    """Per-ray work counters (nodes, surfel tests, k-buffer inserts, rounds)
+    leave the results unchanged and are consistent with them: every
+    composited hit was tested and inserted, and the rounds hold the hits
+    k at a time."""
+    from paper_2412_15867_amd import trace
+    sc, ro, rd = c1
+    note(f"c1 work counters k={k}")
+    scene = make_scene(sc)
+    a = trace(scene, dev(ro), dev(rd), hit_cap=0, k=k, counters=True)
+    b = to_np(trace(scene, dev(ro), dev(rd), hit_cap=0, k=k))
+    torch.cuda.synchronize()
+    c = a.counters.cpu().numpy().astype(np.int64)
+    a = to_np(a)
+    scene.close()
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(a[key], b[key]), key
+    nh = a["n_hits"].astype(np.int64)
+    nodes, tests, inserts, rounds = c.T
+    assert np.all(nodes >= 1) and np.all(rounds >= 1)  # every c1 ray is valid and starts at the root
+    assert np.all(tests >= nh) and np.all(inserts >= nh)
+    assert np.all(rounds >= (nh + k - 1) // k)
+    assert np.all(tests >= inserts)
+
+
 def test_lone_splat_closed_form():
     """A ray through a lone splat's centre returns exactly its opacity."""
     g = np.random.default_rng(20)
