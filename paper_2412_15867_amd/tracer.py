@@ -249,7 +249,10 @@ def trace_backward(scene: Scene, ro, rd, saved: TraceResult, g_opacity=None, g_f
                    cfg: Optional[TraceConfig] = None, grads: Optional[dict] = None, **kw) -> dict:
     """Accumulate dL/d(mu, quat, scale, opacity, feat) for upstream gradients
     of (opacity, feat, depth).  Returns the gradient dict (allocated zeroed
-    when not given)."""
+    when not given).  Rays whose hits fit `saved`'s stored lists replay them;
+    with ``cfg.recompute`` (or no stored lists) the rays are traced again in
+    batches within a transient 4 GiB workspace and replayed; rays longer than
+    the lists re-march, about ten times a forward per ray."""
     cfg = cfg or TraceConfig(**kw)
     R = _rays(scene, ro, rd)
     if saved.n_hits is None:
