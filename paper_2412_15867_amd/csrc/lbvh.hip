@@ -258,10 +258,11 @@ __global__ void k_records(int n, const uint32_t* __restrict__ order, const float
     r.a = make_float4(m.x, m.y, m.z, o);
     r.b = make_float4(nn[0], nn[1], nn[2], rho2max);
     r.c = make_float4(tu[0] / s.x, tu[1] / s.x, tu[2] / s.x, __int_as_float(i));
-    r.d = make_float4(tv[0] / s.y, tv[1] / s.y, tv[2] / s.y, 0.0f);
+    const float inf_slab = __int_as_float(0x7f800000);  // cluster slab, set by k_cluster_slabs
+    r.d = make_float4(tv[0] / s.y, tv[1] / s.y, tv[2] / s.y, inf_slab);
     if (!ok) {
         r.c = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(i));
-        r.d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r.d = make_float4(0.0f, 0.0f, 0.0f, inf_slab);
     }
     rec[p] = r;
     float* bx = leafbox + 6 * static_cast<int64_t>(p);
@@ -466,6 +467,45 @@ __global__ void k_level_up(int cnt, const int* __restrict__ ids, BvhNode* __rest
     node_union(nd, b);
     const int parent = nd.ch.z;
     put_child_box(&nodes[parent], nodes[parent].ch.x == x ? 0 : 1, b);
+}
+
+// Cluster slabs: record i of a leaf cluster stores in its last word the
+// half-thickness h of a slab about its own plane, |n_i.(x - mu_i)| <= h,
+// that holds the support ellipse of every record from i to the end of the
+// cluster (an ellipse mu_j + a s_u t_u + b s_v t_v, a^2 + b^2 <= rho_j^2,
+// reaches rho_j sqrt((s_u n_i.t_u)^2 + (s_v n_i.t_v)^2) off its centre along
+// n_i; the record rows are t/s, so s n.t = n.row / |row|^2).  A ray that does
+// not cross that slab inside its depth window cannot hit any of those
+// records.  Records that never hit are skipped; a record without a plane of
+// its own keeps h = +inf (never culls).
+__global__ void k_cluster_slabs(int nw, const WideNode* __restrict__ wn, SurfelRec* __restrict__ rec)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * nw) return;
+    const int ref = reinterpret_cast<const int*>(&wn[t >> 2].child)[t & 3];
+    if (ref == kNoChild || (ref & kLeafBit) == 0) return;
+    const int first = (ref & ~kLeafBit) >> 4, cnt = (ref & 15) + 1;
+    const float inf = __int_as_float(0x7f800000);
+    for (int i = 0; i < cnt; ++i) {
+        const SurfelRec si = rec[first + i];
+        float h = inf;
+        if (si.b.w >= 0.0f) {
+            const float nx = si.b.x, ny = si.b.y, nz = si.b.z;
+            h = 0.0f;
+            for (int j = i; j < cnt; ++j) {
+                const SurfelRec sj = j == i ? si : rec[first + j];
+                if (sj.b.w < 0.0f) continue;  // never hits
+                const float dc = fabsf(dot3(nx, ny, nz, sj.a.x - si.a.x, sj.a.y - si.a.y, sj.a.z - si.a.z));
+                const float cu = dot3(nx, ny, nz, sj.c.x, sj.c.y, sj.c.z) / dot3(sj.c.x, sj.c.y, sj.c.z, sj.c.x, sj.c.y, sj.c.z);
+                const float cv = dot3(nx, ny, nz, sj.d.x, sj.d.y, sj.d.z) / dot3(sj.d.x, sj.d.y, sj.d.z, sj.d.x, sj.d.y, sj.d.z);
+                h = fmaxf(h, dc + sqrtf(sj.b.w) * sqrtf(fmaf(cu, cu, cv * cv)));
+            }
+            const float m = fmaxf(fmaxf(fabsf(si.a.x), fabsf(si.a.y)), fabsf(si.a.z));
+            h = fmaf(h, 1.001f, 1e-6f * (1.0f + m));  // rounding of the sums above
+            if (!(h < inf)) h = inf;                  // non-finite geometry: never cull
+        }
+        reinterpret_cast<float*>(rec + first + i)[15] = h;
+    }
 }
 
 __global__ void k_depth(int n, const int* __restrict__ leaf_parent, const BvhNode* __restrict__ nodes,
@@ -1067,6 +1107,12 @@ hipError_t lbvh_build(BuildArgs& a, void* scratch, hipStream_t st)
         a.n_wide = nw;
         a.wide_depth = levels;
     }
+    if (a.n_wide > 0) {
+        k_cluster_slabs<<<blocks_for(4 * static_cast<int64_t>(a.n_wide), 256), 256, 0, st>>>(a.n_wide, a.wnodes,
+                                                                                            a.rec);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     e = fill_u32(a.depth, 1, 0u, st);
     if (e != hipSuccess) return e;
     k_depth<<<blocks_for(n, 256), 256, 0, st>>>(n, a.leaf_parent, a.nodes, a.depth);
@@ -1078,7 +1124,9 @@ hipError_t lbvh_refit(const BuildArgs& a, hipStream_t st)
     if (a.n <= 0) return hipSuccess;
     hipError_t e = refit_boxes(a, st);
     if (e != hipSuccess) return e;
+    if (a.n_wide <= 0) return hipGetLastError();
     k_wide_refit<<<blocks_for(a.n_wide, 256), 256, 0, st>>>(a.n_wide, a.wsrc, a.nodes, a.wnodes);
+    k_cluster_slabs<<<blocks_for(4 * static_cast<int64_t>(a.n_wide), 256), 256, 0, st>>>(a.n_wide, a.wnodes, a.rec);
     return hipGetLastError();
 }
 

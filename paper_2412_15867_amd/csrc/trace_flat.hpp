@@ -301,15 +301,25 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const SurfelRec* recs = src.view(lr).rec;
                 const SurfelRec s0 = load_rec(recs, first);
                 const SurfelRec s1 = load_rec(recs, cnt > 1 ? first + 1 : first);
-                int used = 1;
-                ++ct.tests;
-                float tau, rho2;
-                bool hit = hit_test(s0, ray, P.t_min, P.t_max, &tau, &rho2);
+                // The first record's slab holds every disc left in the cluster:
+                // when the ray crosses it only before the window (or the resume
+                // depth) or only after t_max, none of them can be a hit.
+                const float wx = s0.a.x - ray.ox, wy = s0.a.y - ray.oy, wz = s0.a.z - ray.oz;
+                const float num = dot3(s0.b.x, s0.b.y, s0.b.z, wx, wy, wz);
+                const float rden = __builtin_amdgcn_rcpf(dot3(s0.b.x, s0.b.y, s0.b.z, ray.dx, ray.dy, ray.dz));
+                const float h = fmaf(1e-5f, 1.0f + fabsf(wx) + fabsf(wy) + fabsf(wz), s0.d.w);
+                const float ta = (num - h) * rden, tb = (num + h) * rden;
+                const float lo = after == 0 ? P.t_min : fmaxf(P.t_min, key_tau(after));
+                const bool past = (ta < lo && tb < lo) || (ta > P.t_max && tb > P.t_max);
+                int used = past ? cnt : 1;
+                ct.tests += past ? 0 : 1;
+                float tau = 0.0f, rho2 = 0.0f;
+                bool hit = !past && hit_test(s0, ray, P.t_min, P.t_max, &tau, &rho2);
                 uint64_t key = hit_key(tau, first);
                 bool above = hit && key > after;
                 bool ins = above && key < kb.last();
                 if (above && !ins) dq.put(cluster_ref(first, 1));  // beyond this round's K-th key
-                if (!ins && cnt > 1) {
+                if (!past && !ins && cnt > 1) {
                     used = 2;
                     ++ct.tests;
                     hit = hit_test(s1, ray, P.t_min, P.t_max, &tau, &rho2);
