@@ -258,7 +258,7 @@ __global__ void k_records(int n, const uint32_t* __restrict__ order, const float
     r.a = make_float4(m.x, m.y, m.z, o);
     r.b = make_float4(nn[0], nn[1], nn[2], rho2max);
     r.c = make_float4(tu[0] / s.x, tu[1] / s.x, tu[2] / s.x, __int_as_float(i));
-    const float inf_slab = __int_as_float(0x7f800000);  // cluster slab, set by k_cluster_slabs
+    const float inf_slab = __uint_as_float(0x7c007c00u);  // cluster bound (+inf, +inf), set by k_cluster_slabs
     r.d = make_float4(tv[0] / s.y, tv[1] / s.y, tv[2] / s.y, inf_slab);
     if (!ok) {
         r.c = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(i));
@@ -469,15 +469,28 @@ __global__ void k_level_up(int cnt, const int* __restrict__ ids, BvhNode* __rest
     put_child_box(&nodes[parent], nodes[parent].ch.x == x ? 0 : 1, b);
 }
 
-// Cluster slabs: record i of a leaf cluster stores in its last word the
-// half-thickness h of a slab about its own plane, |n_i.(x - mu_i)| <= h,
-// that holds the support ellipse of every record from i to the end of the
-// cluster (an ellipse mu_j + a s_u t_u + b s_v t_v, a^2 + b^2 <= rho_j^2,
-// reaches rho_j sqrt((s_u n_i.t_u)^2 + (s_v n_i.t_v)^2) off its centre along
-// n_i; the record rows are t/s, so s n.t = n.row / |row|^2).  A ray that does
-// not cross that slab inside its depth window cannot hit any of those
-// records.  Records that never hit are skipped; a record without a plane of
-// its own keeps h = +inf (never culls).
+// An FP16 no smaller than x >= 0 (+inf past the FP16 range), as its bits.
+__device__ __forceinline__ uint32_t half_up(float x)
+{
+    if (!(x < 65504.0f)) return 0x7c00u;
+    const _Float16 h = static_cast<_Float16>(x);
+    uint32_t b = __builtin_bit_cast(uint16_t, h);
+    if (static_cast<float>(h) < x) ++b;
+    return b;
+}
+
+// Cluster bounds: record i of a leaf cluster stores in its last word, as two
+// FP16 rounded up, the half-thickness h of a slab about its own plane,
+// |n_i.(x - mu_i)| <= h (low half), and the radius c of a cylinder about the
+// normal through its centre, |P_i (x - mu_i)| <= c with P_i the projection
+// onto the plane (high half), that hold the support ellipse of every record
+// from i to the end of the cluster.  An ellipse mu_j + a s_u t_u + b s_v t_v,
+// a^2 + b^2 <= rho_j^2, reaches rho_j sqrt((s_u n_i.t_u)^2 + (s_v n_i.t_v)^2)
+// off its centre along n_i (the record rows are t/s, so s n.t = n.row /
+// |row|^2) and at most rho_j max(s_u, s_v) across it.  A ray that does not
+// pass through both inside its depth window cannot hit any of those records.
+// Records that never hit are skipped; a record without a plane of its own
+// keeps (+inf, +inf) (never culls).
 __global__ void k_cluster_slabs(int nw, const WideNode* __restrict__ wn, SurfelRec* __restrict__ rec)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -488,23 +501,31 @@ __global__ void k_cluster_slabs(int nw, const WideNode* __restrict__ wn, SurfelR
     const float inf = __int_as_float(0x7f800000);
     for (int i = 0; i < cnt; ++i) {
         const SurfelRec si = rec[first + i];
-        float h = inf;
+        float h = inf, c = inf;
         if (si.b.w >= 0.0f) {
             const float nx = si.b.x, ny = si.b.y, nz = si.b.z;
             h = 0.0f;
+            c = 0.0f;
             for (int j = i; j < cnt; ++j) {
                 const SurfelRec sj = j == i ? si : rec[first + j];
                 if (sj.b.w < 0.0f) continue;  // never hits
-                const float dc = fabsf(dot3(nx, ny, nz, sj.a.x - si.a.x, sj.a.y - si.a.y, sj.a.z - si.a.z));
-                const float cu = dot3(nx, ny, nz, sj.c.x, sj.c.y, sj.c.z) / dot3(sj.c.x, sj.c.y, sj.c.z, sj.c.x, sj.c.y, sj.c.z);
-                const float cv = dot3(nx, ny, nz, sj.d.x, sj.d.y, sj.d.z) / dot3(sj.d.x, sj.d.y, sj.d.z, sj.d.x, sj.d.y, sj.d.z);
-                h = fmaxf(h, dc + sqrtf(sj.b.w) * sqrtf(fmaf(cu, cu, cv * cv)));
+                const float ex = sj.a.x - si.a.x, ey = sj.a.y - si.a.y, ez = sj.a.z - si.a.z;
+                const float dn = dot3(nx, ny, nz, ex, ey, ez);
+                const float uu = dot3(sj.c.x, sj.c.y, sj.c.z, sj.c.x, sj.c.y, sj.c.z);
+                const float vv = dot3(sj.d.x, sj.d.y, sj.d.z, sj.d.x, sj.d.y, sj.d.z);
+                const float cu = dot3(nx, ny, nz, sj.c.x, sj.c.y, sj.c.z) / uu;
+                const float cv = dot3(nx, ny, nz, sj.d.x, sj.d.y, sj.d.z) / vv;
+                const float rho = sqrtf(sj.b.w);
+                h = fmaxf(h, fabsf(dn) + rho * sqrtf(fmaf(cu, cu, cv * cv)));
+                const float px = ex - dn * nx, py = ey - dn * ny, pz = ez - dn * nz;
+                c = fmaxf(c, sqrtf(dot3(px, py, pz, px, py, pz)) + rho * fmaxf(rsqrtf(uu), rsqrtf(vv)));
             }
             const float m = fmaxf(fmaxf(fabsf(si.a.x), fabsf(si.a.y)), fabsf(si.a.z));
             h = fmaf(h, 1.001f, 1e-6f * (1.0f + m));  // rounding of the sums above
-            if (!(h < inf)) h = inf;                  // non-finite geometry: never cull
+            c = fmaf(c, 1.001f, 1e-6f * (1.0f + m));
         }
-        reinterpret_cast<float*>(rec + first + i)[15] = h;
+        // non-finite geometry packs as +inf: never culls
+        reinterpret_cast<uint32_t*>(rec + first + i)[15] = half_up(h) | (half_up(c) << 16);
     }
 }
 
