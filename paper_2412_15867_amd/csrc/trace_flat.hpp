@@ -314,23 +314,15 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const float cr = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hc >> 16))) + pad;
                 const float ta = (num - h) * rden, tb = (num + h) * rden;
                 const float lo = after == 0 ? P.t_min : fmaxf(P.t_min, key_tau(after));
-                // Footprint (k = 64 only: its two waves per SIMD have the
-                // registers to spare; at k <= 32 the test costs occupancy that
-                // it does not repay): the closest approach, across the plane, of
-                // the ray's stretch in the slab to the normal through the first
-                // centre, q(t) = q0 + t q1, beyond the cylinder's radius.
-                bool wide = false;
-                if constexpr (K >= 64) {
-                    const float q0x = fmaf(num, s0.b.x, -wx), q0y = fmaf(num, s0.b.y, -wy),
-                                q0z = fmaf(num, s0.b.z, -wz);
-                    const float q1x = fmaf(-den, s0.b.x, ray.dx), q1y = fmaf(-den, s0.b.y, ray.dy),
-                                q1z = fmaf(-den, s0.b.z, ray.dz);
-                    const float q11 = dot3(q1x, q1y, q1z, q1x, q1y, q1z);
-                    const float ts =
-                        fminf(fmaxf(-dot3(q0x, q0y, q0z, q1x, q1y, q1z) / q11, fminf(ta, tb)), fmaxf(ta, tb));
-                    const float qx = fmaf(ts, q1x, q0x), qy = fmaf(ts, q1y, q0y), qz = fmaf(ts, q1z, q0z);
-                    wide = dot3(qx, qy, qz, qx, qy, qz) > cr * cr * 1.0001f;  // NaN: false
-                }
+                // Footprint: at the slab's middle depth t_c = num / den the ray
+                // is on the first record's plane, at t_c d - w from its centre;
+                // within the slab it moves across the plane by at most
+                // |d| h / |den|.  Farther than that from the cylinder, it
+                // misses every disc left in the cluster.
+                const float tc = num * rden;
+                const float ex = fmaf(tc, ray.dx, -wx), ey = fmaf(tc, ray.dy, -wy), ez = fmaf(tc, ray.dz, -wz);
+                const float reach = fmaf(sqrtf(dot3(ray.dx, ray.dy, ray.dz, ray.dx, ray.dy, ray.dz)), h * fabsf(rden), cr);
+                const bool wide = dot3(ex, ey, ez, ex, ey, ez) > reach * reach * 1.0001f;  // NaN, inf: false
                 const bool past = (ta < lo && tb < lo) || (ta > P.t_max && tb > P.t_max) || wide;
                 int used = past ? cnt : 1;
                 ct.tests += past ? 0 : 1;
