@@ -101,6 +101,32 @@ __device__ __forceinline__ int64_t claim_slot(unsigned long long* next)
     return static_cast<int64_t>(base) + rank;
 }
 
+// True when the ray cannot hit the disc of record s nor any later disc of
+// its leaf cluster inside the depth window (lo, t_max).  The record's last
+// word holds two FP16 bounds of those discs: the half-thickness h of a slab
+// about its plane and the radius c of a cylinder about its normal.  The ray
+// crosses the slab for t in (num -+ h) / den; at the middle depth
+// t_c = num / den it lies on the plane at t_c d - w from the centre and
+// within the slab it moves across the plane by at most |d| h / |den|.  Both
+// bounds take a pad for the rounding of these FP32 depths; a NaN or an
+// infinity from a ray parallel to the plane never culls.
+__device__ __forceinline__ bool cluster_miss(const SurfelRec& s, const Ray& ray, float lo, float t_max)
+{
+    const float wx = s.a.x - ray.ox, wy = s.a.y - ray.oy, wz = s.a.z - ray.oz;
+    const float num = dot3(s.b.x, s.b.y, s.b.z, wx, wy, wz);
+    const float rden = __builtin_amdgcn_rcpf(dot3(s.b.x, s.b.y, s.b.z, ray.dx, ray.dy, ray.dz));
+    const uint32_t hc = __float_as_uint(s.d.w);
+    const float pad = 1e-5f * (1.0f + fabsf(wx) + fabsf(wy) + fabsf(wz));
+    const float h = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hc))) + pad;
+    const float cr = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hc >> 16))) + pad;
+    const float ta = (num - h) * rden, tb = (num + h) * rden;
+    const float tc = num * rden;
+    const float ex = fmaf(tc, ray.dx, -wx), ey = fmaf(tc, ray.dy, -wy), ez = fmaf(tc, ray.dz, -wz);
+    const float reach = fmaf(sqrtf(dot3(ray.dx, ray.dy, ray.dz, ray.dx, ray.dy, ray.dz)), h * fabsf(rden), cr);
+    const bool wide = dot3(ex, ey, ez, ex, ey, ez) > reach * reach * 1.0001f;
+    return (ta < lo && tb < lo) || (ta > t_max && tb > t_max) || wide;
+}
+
 // Stored hit lists are written two entries at a time (one 8-byte store for
 // the ids, one for the transmittances) when rows start 8-byte aligned.
 __device__ __forceinline__ bool pair_stores(const OutPtrs& out)
@@ -301,30 +327,14 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const SurfelRec* recs = src.view(lr).rec;
                 const SurfelRec s0 = load_rec(recs, first);
                 const SurfelRec s1 = load_rec(recs, cnt > 1 ? first + 1 : first);
-                // The first record's slab holds every disc left in the cluster:
-                // when the ray crosses it only before the window (or the resume
-                // depth) or only after t_max, none of them can be a hit.
-                const float wx = s0.a.x - ray.ox, wy = s0.a.y - ray.oy, wz = s0.a.z - ray.oz;
-                const float num = dot3(s0.b.x, s0.b.y, s0.b.z, wx, wy, wz);
-                const float den = dot3(s0.b.x, s0.b.y, s0.b.z, ray.dx, ray.dy, ray.dz);
-                const float rden = __builtin_amdgcn_rcpf(den);
-                const uint32_t hc = __float_as_uint(s0.d.w);
-                const float pad = 1e-5f * (1.0f + fabsf(wx) + fabsf(wy) + fabsf(wz));
-                const float h = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hc))) + pad;
-                const float cr = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hc >> 16))) + pad;
-                const float ta = (num - h) * rden, tb = (num + h) * rden;
+                // Each record's bounds hold its own disc and every later disc of
+                // its cluster: outside the first record's, none of the cluster's
+                // remaining discs can be a hit; outside the second's, none after
+                // the first.
                 const float lo = after == 0 ? P.t_min : fmaxf(P.t_min, key_tau(after));
-                // Footprint: at the slab's middle depth t_c = num / den the ray
-                // is on the first record's plane, at t_c d - w from its centre;
-                // within the slab it moves across the plane by at most
-                // |d| h / |den|.  Farther than that from the cylinder, it
-                // misses every disc left in the cluster.
-                const float tc = num * rden;
-                const float ex = fmaf(tc, ray.dx, -wx), ey = fmaf(tc, ray.dy, -wy), ez = fmaf(tc, ray.dz, -wz);
-                const float reach = fmaf(sqrtf(dot3(ray.dx, ray.dy, ray.dz, ray.dx, ray.dy, ray.dz)), h * fabsf(rden), cr);
-                const bool wide = dot3(ex, ey, ez, ex, ey, ez) > reach * reach * 1.0001f;  // NaN, inf: false
-                const bool past = (ta < lo && tb < lo) || (ta > P.t_max && tb > P.t_max) || wide;
-                int used = past ? cnt : 1;
+                const bool past = cluster_miss(s0, ray, lo, P.t_max);
+                const bool past1 = !past && cnt > 1 && cluster_miss(s1, ray, lo, P.t_max);
+                int used = past || past1 ? cnt : 1;
                 ct.tests += past ? 0 : 1;
                 float tau = 0.0f, rho2 = 0.0f;
                 bool hit = !past && hit_test(s0, ray, P.t_min, P.t_max, &tau, &rho2);
@@ -332,7 +342,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 bool above = hit && key > after;
                 bool ins = above && key < kb.last();
                 if (above && !ins) dq.put(cluster_ref(first, 1));  // beyond this round's K-th key
-                if (!past && !ins && cnt > 1) {
+                if (!past && !past1 && !ins && cnt > 1) {
                     used = 2;
                     ++ct.tests;
                     hit = hit_test(s1, ray, P.t_min, P.t_max, &tau, &rho2);
