@@ -615,6 +615,7 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
     if (p->feature_dim < Fmax) return fail(IRGS_E_INVALID, "feature_dim %d < largest scene F %d", p->feature_dim, Fmax);
     std::vector<WorkItem> w(n_items);
     int64_t chunks = 0;
+    bool counters = false;
     for (int i = 0; i < n_items; ++i) {
         const irgs_work& it = items[i];
         if (it.scene < 0 || it.scene >= n_scenes) return fail(IRGS_E_INVALID, "item %d: bad scene %d", i, it.scene);
@@ -629,6 +630,7 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
         w[i].ro = it.ro;
         w[i].rd = it.rd;
         w[i].out = out_ptrs(&it.out);
+        counters = counters || it.out.counters != nullptr;
         chunks += it.ray_count;
     }
     if (chunks == 0) return IRGS_OK;
@@ -651,7 +653,8 @@ irgs_status irgs_trace_packed(const irgs_scene* scenes, int32_t n_scenes, const 
     if (e == hipSuccess) e = hipMemcpyAsync(ditems, w.data(), wb, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) {
         TraceParams tp = trace_params(p, Fmax);
-        e = launch_packed(dviews, ditems, n_items, chunks, tp, p->k, flat_scratch(ovf.p, slots, dq.p), grid, hs);
+        e = launch_packed(dviews, ditems, n_items, chunks, tp, p->k, flat_scratch(ovf.p, slots, dq.p), grid, counters,
+                          hs);
     }
     if (e != hipSuccess) return hip_fail(e, "packed launch");
     return IRGS_OK;

@@ -172,8 +172,10 @@ struct WorkItem {
     OutPtrs out;
 };
 
+// counters: some item asks for work counters.
 hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_rays,
-                         const TraceParams& P, int k, const FlatScratch& fs, int grid_blocks, hipStream_t st);
+                         const TraceParams& P, int k, const FlatScratch& fs, int grid_blocks, bool counters,
+                         hipStream_t st);
 
 // Monte Carlo rendering-equation consumer (shade.hip).
 struct ShadeArgs {

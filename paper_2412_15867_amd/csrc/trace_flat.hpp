@@ -135,7 +135,7 @@ __device__ __forceinline__ bool pair_stores(const OutPtrs& out)
     return (out.H_cap & 1) == 0 && (a & 7) == 0;
 }
 
-template <int FM, int CM, class Source>
+template <int FM, int CM, bool CT, class Source>
 __device__ __forceinline__ void write_result(const Source& src, const LaneRay& lr, float O, float D, float T,
                                              const float* acc, int nh, const Counters& ct)
 {
@@ -150,7 +150,7 @@ __device__ __forceinline__ void write_result(const Source& src, const LaneRay& l
         if (c < FO) out.feat[r * FO + c] = acc[c];
     if (out.T) out.T[r] = T;
     if (out.n_hits) out.n_hits[r] = nh;
-    if (out.counters)
+    if (CT && out.counters)
         reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
 }
 
@@ -218,7 +218,9 @@ struct Deferred {
     }
 };
 
-template <int K, int FM, int CM, class Source>
+// CT: keep the per-ray work counters (launches that ask for them); without,
+// their registers stay free.
+template <int K, int FM, int CM, bool CT, class Source>
 __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long* next_ray, const TraceParams& P,
                                            Stack& st, Deferred dq)
 {
@@ -256,7 +258,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         if (__ballot(want_ins)) {
             const uint64_t ev = kb.insert_if(want_ins, pend);
             if (want_ins) {
-                ++ct.inserts;
+                if constexpr (CT) ++ct.inserts;
                 if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
                 pend = kKeyNone;
                 mode = kTrav;
@@ -274,7 +276,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
         if (cn >= cl && cn >= co) {
             if (want_node) {
-                ++ct.nodes;
+                if constexpr (CT) ++ct.nodes;
                 const float4* np = reinterpret_cast<const float4*>(src.view(lr).wnodes + cur);
                 const float4 lx = np[0], ly = np[1], lz = np[2], hx = np[3], hy = np[4], hz = np[5];
                 const int4 ch = reinterpret_cast<const int4*>(np)[6];
@@ -335,7 +337,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 const bool past = cluster_miss(s0, ray, lo, P.t_max);
                 const bool past1 = !past && cnt > 1 && cluster_miss(s1, ray, lo, P.t_max);
                 int used = past || past1 ? cnt : 1;
-                ct.tests += past ? 0 : 1;
+                if constexpr (CT) ct.tests += past ? 0 : 1;
                 float tau = 0.0f, rho2 = 0.0f;
                 bool hit = !past && hit_test(s0, ray, P.t_min, P.t_max, &tau, &rho2);
                 uint64_t key = hit_key(tau, first);
@@ -344,7 +346,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 if (above && !ins) dq.put(cluster_ref(first, 1));  // beyond this round's K-th key
                 if (!past && !past1 && !ins && cnt > 1) {
                     used = 2;
-                    ++ct.tests;
+                    if constexpr (CT) ++ct.tests;
                     hit = hit_test(s1, ray, P.t_min, P.t_max, &tau, &rho2);
                     key = hit_key(tau, first + 1);
                     above = hit && key > after;
@@ -371,12 +373,12 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     kb.clear();
                     dq.reset();
                     if (src.view(lr).n <= 0 || !ray_valid(ray)) {
-                        write_result<FM, CM>(src, lr, O, D, T, acc, nh, ct);
+                        write_result<FM, CM, CT>(src, lr, O, D, T, acc, nh, ct);
                     } else {
                         q = slab_ray(ray);
                         cur = 0;
                         st.sp = 0;
-                        ++ct.rounds;
+                        if constexpr (CT) ++ct.rounds;
                         mode = kTrav;
                     }
                 }
@@ -422,12 +424,12 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     out.hit_ids[lr.r * out.H_cap + nh - 1] = pend_id;
                     if (out.hit_T) out.hit_T[lr.r * out.H_cap + nh - 1] = pend_T;
                 }
-                write_result<FM, CM>(src, lr, O, D, T, acc, nh, ct);
+                write_result<FM, CM, CT>(src, lr, O, D, T, acc, nh, ct);
                 mode = kFetch;
             } else {
                 kb.clear();  // `after` is the round's last (K-th) key
                 st.sp = 0;
-                ++ct.rounds;
+                if constexpr (CT) ++ct.rounds;
                 cur = dq.flip() ? next_item() : 0;  // deferred list, or the root after an overflow
                 mode = kTrav;
             }

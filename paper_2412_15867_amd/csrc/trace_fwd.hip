@@ -88,7 +88,7 @@ __device__ __forceinline__ void trace_one(const SceneView& sc, const TraceParams
         reinterpret_cast<int4*>(out.counters)[r] = make_int4(ct.nodes, ct.tests, ct.inserts, ct.rounds);
 }
 
-template <int K, int FM, bool BVH, int CM>
+template <int K, int FM, bool BVH, int CM, bool CT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 && FM <= 8 ? 4 : 1))) void k_trace(SceneView sc, TraceParams P, int64_t R,
                                                   const float* __restrict__ ro, const float* __restrict__ rd,
                                                   OutPtrs out, FlatScratch fs)
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 
     if (BVH) {
         const PlainSource src{sc, out, ro, rd, R, fs.order};
         Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
-        trace_flat<K, FM, CM>(src, fs.next_ray, P, st, dq);
+        trace_flat<K, FM, CM, CT>(src, fs.next_ray, P, st, dq);
     } else {
         for (int64_t r = gtid; r < R; r += nthr) {
             const Ray ray = load_ray(ro, rd, r);
@@ -110,17 +110,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 
     }
 }
 
-template <int K, int FM, bool BVH, int CM>
-hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
-                     const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
+template <int K, int FM, bool BVH, int CM, bool CT>
+hipError_t launch_kct(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
+                      const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
 {
     if (BVH) {
         const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
         if (e != hipSuccess) return e;
     }
-    const unsigned grid = persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH, CM>, kBlock));
-    k_trace<K, FM, BVH, CM><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, fs);
+    const unsigned grid =
+        persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH, CM, CT>, kBlock));
+    k_trace<K, FM, BVH, CM, CT><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, fs);
     return hipGetLastError();
+}
+
+// BVH launches that do not ask for work counters run an instance without
+// them (their four registers free; the plain tracer keeps its own).
+template <int K, int FM, bool BVH, int CM>
+hipError_t launch_kf(const SceneView& sc, const TraceParams& P, int64_t R, const float* ro, const float* rd,
+                     const OutPtrs& out, const FlatScratch& fs, hipStream_t st)
+{
+    if constexpr (BVH) {
+        if (!out.counters) return launch_kct<K, FM, BVH, CM, false>(sc, P, R, ro, rd, out, fs, st);
+    }
+    return launch_kct<K, FM, BVH, CM, true>(sc, P, R, ro, rd, out, fs, st);
 }
 
 template <int K, bool BVH>
@@ -163,7 +176,7 @@ hipError_t launch_b(const SceneView& sc, const TraceParams& P, int k, int64_t R,
 // Packed persistent launch: lanes claim slots of the concatenation of every
 // work item's rays (an item is one request on one scene), so different
 // requests and scenes share one launch.
-template <int K, int FM>
+template <int K, int FM, bool CT>
 __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__ scenes,
                                                    const WorkItem* __restrict__ items, int n_items,
                                                    int64_t n_rays, TraceParams P, FlatScratch fs)
@@ -175,32 +188,42 @@ __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__
              static_cast<int>(threadIdx.x), 0, kStackLds};
     const PackedSource src{scenes, items, n_items, n_rays};
     Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
-    trace_flat<K, FM, kColPlain>(src, fs.next_ray, P, st, dq);
+    trace_flat<K, FM, kColPlain, CT>(src, fs.next_ray, P, st, dq);
+}
+
+template <int K, int FM, bool CT>
+hipError_t launch_packed_kct(const SceneView* scenes, const WorkItem* items, int n_items, int64_t n_rays,
+                             const TraceParams& P, const FlatScratch& fs, int grid_blocks, hipStream_t st)
+{
+    const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
+    if (e != hipSuccess) return e;
+    const unsigned grid = persistent_grid(grid_blocks, resident_blocks(k_packed<K, FM, CT>, kBlock));
+    k_packed<K, FM, CT><<<grid, kBlock, 0, st>>>(scenes, items, n_items, n_rays, P, fs);
+    return hipGetLastError();
 }
 
 template <int K, int FM>
 hipError_t launch_packed_kf(const SceneView* scenes, const WorkItem* items, int n_items, int64_t n_rays,
-                            const TraceParams& P, const FlatScratch& fs, int grid_blocks, hipStream_t st)
+                            const TraceParams& P, const FlatScratch& fs, int grid_blocks, bool counters,
+                            hipStream_t st)
 {
-    const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
-    if (e != hipSuccess) return e;
-    const unsigned grid = persistent_grid(grid_blocks, resident_blocks(k_packed<K, FM>, kBlock));
-    k_packed<K, FM><<<grid, kBlock, 0, st>>>(scenes, items, n_items, n_rays, P, fs);
-    return hipGetLastError();
+    return counters ? launch_packed_kct<K, FM, true>(scenes, items, n_items, n_rays, P, fs, grid_blocks, st)
+                    : launch_packed_kct<K, FM, false>(scenes, items, n_items, n_rays, P, fs, grid_blocks, st);
 }
 
 }  // namespace
 
 hipError_t launch_packed(const SceneView* scenes_dev, const WorkItem* items_dev, int n_items, int64_t n_rays,
-                         const TraceParams& P, int k, const FlatScratch& fs, int grid_blocks, hipStream_t st)
+                         const TraceParams& P, int k, const FlatScratch& fs, int grid_blocks, bool counters,
+                         hipStream_t st)
 {
     if (n_rays <= 0 || n_items <= 0) return hipSuccess;
-    if (k == 16 && P.F <= 8) return launch_packed_kf<16, 8>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
-    if (k == 16 && P.F <= 64)
-        return launch_packed_kf<16, 64>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
-    if (k == 32 && P.F <= 8) return launch_packed_kf<32, 8>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
-    if (k == 32 && P.F <= 64)
-        return launch_packed_kf<32, 64>(scenes_dev, items_dev, n_items, n_rays, P, fs, grid_blocks, st);
+    const SceneView* sv = scenes_dev;
+    const WorkItem* it = items_dev;
+    if (k == 16 && P.F <= 8) return launch_packed_kf<16, 8>(sv, it, n_items, n_rays, P, fs, grid_blocks, counters, st);
+    if (k == 16 && P.F <= 64) return launch_packed_kf<16, 64>(sv, it, n_items, n_rays, P, fs, grid_blocks, counters, st);
+    if (k == 32 && P.F <= 8) return launch_packed_kf<32, 8>(sv, it, n_items, n_rays, P, fs, grid_blocks, counters, st);
+    if (k == 32 && P.F <= 64) return launch_packed_kf<32, 64>(sv, it, n_items, n_rays, P, fs, grid_blocks, counters, st);
     return hipErrorInvalidValue;
 }
 
