@@ -345,3 +345,23 @@ def sky_uniforms(P: int, N: int, seed: int = SEED_PBR + 2) -> np.ndarray:
     from a sky's intensity (texel choice, then the point in the texel)."""
     return _rng(seed).random((P, N, 3)).astype(np.float32)
 
+
+
+def grazing_rays(points: int, cos_lo: float = 1e-4, cos_hi: float = 2e-2, seed: int = SEED_MC_RAYS + 7,
+                 lay: Layout | None = None):
+    """Rays that skim their own surface: area-uniform surface points (planes:
+    random side), directions at cos(theta) ~ U[cos_lo, cos_hi] to the normal
+    with uniform azimuth, origin x + 1e-3 n.  The slowest rays of the
+    Monte Carlo workloads look like these.  Returns float32 (ro, rd)."""
+    if lay is None:
+        lay = layout()
+    g = _rng(seed)
+    x, nn, sid = _sample_surface(g, lay, points)
+    flip = np.where((sid >= 8) & (g.random(points) < 0.5), -1.0, 1.0)
+    nn = nn * flip[:, None]
+    b1, b2 = onb(nn)
+    c = g.uniform(cos_lo, cos_hi, points)
+    phi = g.uniform(0.0, 2.0 * np.pi, points)
+    s = np.sqrt(1.0 - c * c)
+    d = _unit((s * np.cos(phi))[:, None] * b1 + (s * np.sin(phi))[:, None] * b2 + c[:, None] * nn)
+    return _f32(x + 1e-3 * nn), _f32(d)
