@@ -72,7 +72,7 @@ typedef struct {
  *   t_min, t_max  hits need t_min < tau < t_max
  *   support_sigma hits need u^2 + v^2 <= support_sigma^2
  *   flags         IRGS_FLAG_* below
- *   leaf_size     build only: surfels per BVH leaf cluster, 1..16 (0 = 8)
+ *   leaf_size     build only: surfels per BVH leaf cluster, 1..16 (0 = 12)
  * alpha_min and support_sigma are fixed at build time (they size the boxes);
  * tracing with other values returns IRGS_E_STATE. */
 typedef struct {

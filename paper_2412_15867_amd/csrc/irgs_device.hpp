@@ -56,7 +56,7 @@ struct __align__(16) WideNode {
     int4 meta;  // unused
 };
 
-constexpr int kLeafDefault = 8;  // surfels per cluster leaf (at most 16)
+constexpr int kLeafDefault = 12;  // surfels per cluster leaf (at most 16)
 
 __host__ __device__ __forceinline__ int cluster_ref(int first, int count)
 {
