@@ -8,9 +8,10 @@
 // unit of its own work:
 //   TRAV  visit one wide node (4 box tests; children pushed far to near, the
 //         nearest becomes the current item) or test up to two surfels of a
-//         cluster (both records in one round trip); a hit for the buffer
-//         enters it at the top of the next iteration; an empty stack ends
-//         the round;
+//         cluster (both records in one round trip), skipping the rest of the
+//         cluster when the records' bounds show that the ray cannot hit it
+//         inside its depth window; a hit for the buffer enters it at the top
+//         of the next iteration; an empty stack ends the round;
 //   COMP  composite the nearest buffered hit (Eq. 2: w = T alpha, T *= 1 - a)
 //         or, with the buffer drained, start the next round or finish the ray;
 //   FETCH claim the lane's next ray from a global counter (rays go to lanes
