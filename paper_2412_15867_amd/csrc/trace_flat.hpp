@@ -275,7 +275,9 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         const uint64_t bn = __ballot(want_node), bl = __ballot(want_leaf), bo = __ballot(want_other);
         if ((bn | bl | bo) == 0) break;
         const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
-        if (cn >= cl && cn >= co) {
+        // node steps count double against leaf steps: a node step hands its
+        // lanes new items, and a leaf step that waits loses nothing
+        if (cn > 0 && 2 * cn >= cl && cn >= co) {
             if (want_node) {
                 if constexpr (CT) ++ct.nodes;
                 const float4* np = reinterpret_cast<const float4*>(src.view(lr).wnodes + cur);
