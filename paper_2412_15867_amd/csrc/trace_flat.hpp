@@ -276,8 +276,11 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         if ((bn | bl | bo) == 0) break;
         const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
         // node steps count double against leaf steps: a node step hands its
-        // lanes new items, and a leaf step that waits loses nothing
-        if (cn > 0 && 2 * cn >= cl && cn >= co) {
+        // lanes new items, and a leaf step that waits loses nothing; with the
+        // normal channels (relighting) compositing and fetch steps count
+        // double too
+        constexpr int kOtherW = CM == kColNormal ? 2 : 1;
+        if (cn > 0 && 2 * cn >= cl && cn >= kOtherW * co) {
             if (want_node) {
                 if constexpr (CT) ++ct.nodes;
                 const float4* np = reinterpret_cast<const float4*>(src.view(lr).wnodes + cur);
@@ -320,7 +323,7 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 if (key[1] < inf) st.push(ref[1]);
                 cur = key[0] < inf ? ref[0] : next_item();
             }
-        } else if (cl >= co) {
+        } else if (cl >= kOtherW * co) {
             // Test the next surfels of the current cluster: both records of
             // a pair are fetched together (one memory round trip), the
             // second is tested only if the first does not enter the buffer.
