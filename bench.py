@@ -150,10 +150,23 @@ def cpu_baseline(sc, ro, rd, gO, gF, gD, budget_s: float = 12.0, sh_deg: int = -
     lists = lists[:, :max(1, int(r["n_hits"].max()))]
     ograd.grad_given_hits(sc.astuple(), ro[idx], rd[idx], lists, gO[idx], gF[idx], gD[idx], sh_deg=sh_deg)
     t2 = time.perf_counter()
-    return dict(value=round(n / (t2 - t0) / 1e6, 9), unit="Mrays/s", cores=int(threads), kind="oracle",
+    return dict(value=round(n / (t2 - t0) / 1e6, 9), unit="Mrays/s", cores=int(threads), cpu_model=cpu_model(),
+                kind="oracle",
                 sample=f"{n} of the {ro.shape[0]} rays (seeded), brute force over all {sc.n} surfels, FP64 "
                        f"forward {t1 - t0:.2f}s + autograd backward {t2 - t1:.2f}s",
                 fwd_value=round(n / (t1 - t0) / 1e6, 9))
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def gen_surface_workload(n_surfels, points, dirs, F=8):
@@ -307,6 +320,7 @@ def run_c3(args):
                      "l2_hit_rate": measured_l2_hit_rate() if dom_is_fwd and not sh else None,
                      "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": round(dom_ms, 3)},
         "roofline_fwd": {"achieved": round(fb / (fwd_only_ms * 1e-3) / 1e9, 3), "bytes": fb},
+        "max_memory_allocated_gib": round(torch.cuda.max_memory_allocated(dev) / 2**30, 3),
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample")

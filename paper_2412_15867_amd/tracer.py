@@ -290,22 +290,30 @@ class TraceFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, mu, quat, scale, opacity, feat, ro, rd, scene: Scene, cfg: Optional[TraceConfig] = None):
         cfg = cfg or TraceConfig()
-        for a, b in ((mu, scene.mu), (quat, scene.quat), (scale, scene.scale), (feat, scene.feat)):
+        for a, b in ((mu, scene.mu), (quat, scene.quat), (scale, scene.scale), (opacity, scene.opacity),
+                     (feat, scene.feat)):
             if a.data_ptr() != b.data_ptr():
                 raise ValueError("TraceFn inputs must be the scene's own parameter tensors")
         hit_cap = 0 if cfg.recompute else int(cfg.hit_cap)
         res = trace(scene, ro, rd, cfg, hit_cap=hit_cap)
-        ctx.scene, ctx.cfg, ctx.res = scene, cfg, res
-        ctx.save_for_backward(ro, rd)
+        ctx.scene, ctx.cfg = scene, cfg
+        ctx.opacity_shape = opacity.shape
+        # Everything the backward reads goes through save_for_backward, which
+        # holds the returned tensors without a reference back to this node
+        # and frees the lot after a backward that does not retain the graph.
+        # Keeping them as ctx attributes would close a cycle (output ->
+        # grad_fn -> ctx -> output) that keeps every step's hit lists alive
+        # until a cyclic collection.
+        ctx.save_for_backward(ro, rd, res.opacity, res.feat, res.depth, res.T, res.n_hits, res.hit_ids, res.hit_T)
         return res.opacity, res.feat, res.depth
 
     @staticmethod
     def backward(ctx, gO, gF, gD):
-        ro, rd = ctx.saved_tensors
-        scene = ctx.scene
+        ro, rd, O, Fo, D, T, n_hits, hit_ids, hit_T = ctx.saved_tensors
+        saved = TraceResult(O, Fo, D, T, n_hits, hit_ids, hit_T)
         c = lambda t: None if t is None else t.contiguous()
-        grads = trace_backward(scene, ro, rd, ctx.res, c(gO), c(gF), c(gD), cfg=ctx.cfg)
-        return (grads["mu"], grads["quat"], grads["scale"], grads["opacity"].reshape(ctx.scene.opacity.shape),
+        grads = trace_backward(ctx.scene, ro, rd, saved, c(gO), c(gF), c(gD), cfg=ctx.cfg)
+        return (grads["mu"], grads["quat"], grads["scale"], grads["opacity"].reshape(ctx.opacity_shape),
                 grads["feat"], None, None, None, None)
 
 

@@ -267,3 +267,43 @@ def test_full_size_headline_config_sampled():
             floor = np.abs(b).mean() + 1e-30
             err = np.abs(a - b) / (np.abs(b) + floor)
             assert err.max() <= 1e-3, (name, err.max())
+
+
+def test_autograd_loop_memory_flat():
+    """A Stage II style loop (Sec. 3.3: the trace is differentiated every
+    iteration): 30 TraceFn forward + backward steps over 1,048,576 rays with
+    stored hit lists.  Without a cyclic garbage collection the device memory
+    in use after each step must equal that after the first: no step's outputs
+    or hit lists outlive it."""
+    import gc
+    from paper_2412_15867_amd import Scene, TraceConfig, TraceFn
+    lay = synth.layout()
+    sc = synth.surface_scene(200_000, F=8, lay=lay)
+    ro, rd = synth.mc_rays(128 * 128, 64, lay=lay)
+    R = ro.shape[0]
+    gO, gF, gD, _ = synth.upstream(R, 8)
+    params = [dev(x).requires_grad_(True) for x in sc.astuple()]
+    scene = Scene(*[p.detach() for p in params])
+    scene.set_params(*params)
+    ro_d, rd_d, g = dev(ro), dev(rd), [dev(x) for x in (gO, gF, gD)]
+    cfg = TraceConfig(k=16, hit_cap=128)
+    note("TraceFn loop, 30 steps")
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        base = None
+        for step in range(30):
+            for p in params:
+                p.grad = None
+            O, Fo, D = TraceFn.apply(*params, ro_d, rd_d, scene, cfg)
+            torch.autograd.backward([O, Fo, D], g)
+            del O, Fo, D
+            torch.cuda.synchronize()
+            used = torch.cuda.memory_allocated()
+            if base is None:
+                base = used
+            assert used == base, f"step {step}: {used - base} bytes more in use than after step 0"
+    finally:
+        if was:
+            gc.enable()
+    scene.close()
