@@ -222,6 +222,24 @@ irgs_status irgs_scene_refit(irgs_scene scene, void* stream);
 irgs_status irgs_trace(irgs_scene scene, const irgs_params* params, int64_t R, const float* ro, const float* rd,
                        const irgs_out* out, void* stream);
 
+/* irgs_trace for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (bit for bit) as irgs_trace, but the call
+ * allocates nothing: its scratch (the ray-claim counter, each persistent
+ * thread's traversal-stack overflow and deferred-work lists) lives in one
+ * 64 MiB array inside the library's code object, one copy per device, held
+ * until the process ends.  The launch fits its grid and deferred-list length
+ * into that array (resident blocks are dropped only when even 32 entries per
+ * list do not fit them all), so any R is accepted; a scene whose tree is so
+ * deep that one block's stack overflow does not fit returns IRGS_E_INVALID.
+ * IRGS_FLAG_SORT_RAYS needs a per-ray workspace and returns IRGS_E_INVALID.
+ * The claim counter is cleared by a fill kernel on `stream` before each
+ * launch (no memset node).  Every call on one device shares that device's
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and give undefined results; order them on one stream. */
+irgs_status irgs_trace_noalloc(irgs_scene scene, const irgs_params* params, int64_t R, const float* ro,
+                               const float* rd, const irgs_out* out, void* stream);
+
 /* Backward of irgs_trace over the same rays: accumulates parameter
  * gradients.  `saved` is the irgs_out of the forward call: n_hits is
  * required; with hit_ids and hit_T present (and IRGS_FLAG_RECOMPUTE unset)

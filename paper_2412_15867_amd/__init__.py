@@ -13,11 +13,11 @@ HIP library.
 """
 import importlib
 
-__all__ = ["Scene", "TraceConfig", "TraceResult", "TraceFn", "trace", "trace_backward", "trace_packed",
+__all__ = ["Scene", "TraceConfig", "TraceResult", "TraceFn", "trace", "trace_noalloc", "trace_backward", "trace_packed",
            "alloc_result", "synth", "serve", "mc_rays", "shade", "shade_backward", "ShadeFn", "render_pbr",
            "env_prefilter", "brdf_table", "relight_lind", "relight"]
 
-_TRACE_NAMES = {"Scene", "TraceConfig", "TraceResult", "TraceFn", "trace", "trace_backward", "trace_packed",
+_TRACE_NAMES = {"Scene", "TraceConfig", "TraceResult", "TraceFn", "trace", "trace_noalloc", "trace_backward", "trace_packed",
                 "alloc_result"}
 
 

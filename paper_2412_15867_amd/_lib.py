@@ -73,6 +73,8 @@ SIGNATURES = {
     "irgs_scene_build": (ctypes.c_int, [c_vp, ctypes.POINTER(Params), c_vp]),
     "irgs_scene_refit": (ctypes.c_int, [c_vp, c_vp]),
     "irgs_trace": (ctypes.c_int, [c_vp, ctypes.POINTER(Params), c_i64, c_vp, c_vp, ctypes.POINTER(Out), c_vp]),
+    "irgs_trace_noalloc": (ctypes.c_int, [c_vp, ctypes.POINTER(Params), c_i64, c_vp, c_vp, ctypes.POINTER(Out),
+                                          c_vp]),
     "irgs_trace_backward": (ctypes.c_int, [c_vp, ctypes.POINTER(Params), c_i64, c_vp, c_vp, ctypes.POINTER(Out),
                                            ctypes.POINTER(GradIn), ctypes.POINTER(Grads), c_vp]),
     "irgs_trace_packed": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32, ctypes.POINTER(Params),

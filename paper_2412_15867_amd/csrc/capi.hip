@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -196,6 +197,8 @@ FlatScratch flat_scratch(void* ovf, int slots, void* dq)
     f.ovf_slots = slots;
     f.next_ray = static_cast<unsigned long long*>(dq);
     f.dbuf = dq ? reinterpret_cast<int*>(static_cast<char*>(dq) + kClaimBytes) : nullptr;
+    f.defer_cap = kDeferCap;
+    f.fixed_words = 0;
     return f;
 }
 
@@ -240,6 +243,41 @@ TraceParams trace_params(const irgs_params* p, int32_t F)
     t.sh_deg = (p->flags & IRGS_FLAG_SH) ? sh_degree(F) : -1;
     t.normals = (p->flags & IRGS_FLAG_NORMAL) ? 1 : 0;
     return t;
+}
+
+// Scratch of irgs_trace_noalloc: the ray-claim counter, then every
+// thread's stack overflow and deferred lists.  One copy per device, held by
+// the library's code object until the process ends; host code uses only the
+// device address looked up per device (the array's name is a host-side
+// stand-in that no kernel may be handed).
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+namespace {
+
+// Device address of the no-alloc scratch on the current device, looked up
+// once per device with that device current.
+irgs_status noalloc_scratch_ptr(char** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(IRGS_E_INVALID, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "no-alloc scratch lookup");
+        g_noalloc_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return IRGS_OK;
 }
 
 struct AsyncBuf {
@@ -510,6 +548,36 @@ irgs_status irgs_trace(irgs_scene s, const irgs_params* p, int64_t R, const floa
         if (e != hipSuccess) return hip_fail(e, "ray order");
     }
     e = launch_trace(sv, trace_params(p, s->F), p->k, bvh, R, ro, rd, out_ptrs(out), fs, hs);
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return IRGS_OK;
+}
+
+irgs_status irgs_trace_noalloc(irgs_scene s, const irgs_params* p, int64_t R, const float* ro, const float* rd,
+                               const irgs_out* out, void* stream)
+{
+    irgs_status st = check_trace_common(s, p, R, ro, rd);
+    if (st != IRGS_OK) return st;
+    if (!out) return fail(IRGS_E_INVALID, "out is NULL");
+    if (R > 0 && (!out->opacity || !out->feat || !out->depth))
+        return fail(IRGS_E_INVALID, "out->opacity, feat and depth are required");
+    if (out->hit_ids && out->H_cap < 0) return fail(IRGS_E_INVALID, "H_cap < 0");
+    if (p->flags & IRGS_FLAG_SORT_RAYS)
+        return fail(IRGS_E_INVALID, "IRGS_FLAG_SORT_RAYS needs a per-ray workspace: use irgs_trace");
+    const bool bvh = !(p->flags & IRGS_FLAG_BRUTE_FORCE);
+    const int slots = bvh ? ovf_slots_of(s) : 0;
+    const size_t words = (kNoAllocBytes - kClaimBytes) / sizeof(int);
+    if (bvh && !fixed_scratch_fits(words, slots, kBlock))
+        return fail(IRGS_E_INVALID, "scene tree too deep for the %zu-byte no-alloc scratch (%d overflow slots per thread)",
+                    kNoAllocBytes, slots);
+    if (R == 0) return IRGS_OK;
+    char* base = nullptr;
+    st = noalloc_scratch_ptr(&base);
+    if (st != IRGS_OK) return st;
+    FlatScratch fs = flat_scratch(base + kClaimBytes, slots, base);
+    fs.dbuf = nullptr;  // placed by the launch after every thread's overflow slots
+    fs.fixed_words = words;
+    const hipError_t e = launch_trace(view_of(s), trace_params(p, s->F), p->k, bvh, R, ro, rd, out_ptrs(out), fs,
+                                      static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return IRGS_OK;
 }

@@ -108,13 +108,31 @@ inline unsigned persistent_grid(int64_t max_blocks, int64_t resident)
 // Device scratch of a persistent forward launch, sized for trace_threads(R)
 // threads (the launch may use fewer).
 constexpr int kDeferCap = 192;
+// Smallest deferred-list half a launch into a fixed scratch area takes
+// before it gives up resident blocks instead.
+constexpr int kDeferCapMin = 32;
 struct FlatScratch {
     int* ovf;                      // stack overflow: ovf_slots ints per thread, or null when ovf_slots == 0
     int ovf_slots;
-    int* dbuf;                     // deferred-work lists: 2 * kDeferCap ints per thread (BVH launches)
+    int* dbuf;                     // deferred-work lists: 2 * defer_cap ints per thread (BVH launches)
     unsigned long long* next_ray;  // ray-claim counter (BVH launches); the launch zeroes it
     const uint32_t* order;         // optional claim order (slot -> ray), BVH launches over one scene
+    int defer_cap;                 // entries per half of a thread's deferred list
+    // 0: ovf and dbuf are sized for trace_threads(R) threads at defer_cap.
+    // Otherwise they share one area of this many ints (ovf first, dbuf
+    // right after it, placed by the launch): the launch picks its grid and
+    // the deferred-list size so that both fit (fewer resident blocks only
+    // when even kDeferCapMin entries per half do not fit every one).
+    size_t fixed_words;
 };
+
+// True when a launch into a fixed area of `words` ints can run at least one
+// block (its threads' stack overflow and deferred-list halves of
+// kDeferCapMin entries).
+inline bool fixed_scratch_fits(size_t words, int ovf_slots, int block)
+{
+    return words >= static_cast<size_t>(block) * (ovf_slots + 2 * kDeferCapMin);
+}
 
 // Claim order of a forward trace: rays sorted by the Morton code of their
 // origin in the scene's root box.  `buf` holds ray_sort_words(R) floats;

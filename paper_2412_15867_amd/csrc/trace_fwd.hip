@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 
              static_cast<int>(threadIdx.x), 0, kStackLds};
     if (BVH) {
         const PlainSource src{sc, out, ro, rd, R, fs.order};
-        Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
+        Deferred dq{as_glb(fs.dbuf + gtid * 2 * fs.defer_cap), fs.defer_cap, 0, 0, 0, 0};
         trace_flat<K, FM, CM, CT>(src, fs.next_ray, P, st, dq);
     } else {
         for (int64_t r = gtid; r < R; r += nthr) {
@@ -118,9 +118,24 @@ hipError_t launch_kct(const SceneView& sc, const TraceParams& P, int64_t R, cons
         const hipError_t e = fill_u32(fs.next_ray, 2, 0u, st);
         if (e != hipSuccess) return e;
     }
-    const unsigned grid =
-        persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH, CM, CT>, kBlock));
-    k_trace<K, FM, BVH, CM, CT><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, fs);
+    unsigned grid = persistent_grid(trace_threads(R) / kBlock, resident_blocks(k_trace<K, FM, BVH, CM, CT>, kBlock));
+    FlatScratch f = fs;
+    if (BVH && fs.fixed_words > 0) {
+        // One fixed area: the stack overflow of every thread, then the
+        // deferred lists.  Keep every resident block while a half of at
+        // least kDeferCapMin entries fits, else drop blocks.
+        const size_t per_block_min = static_cast<size_t>(kBlock) * (fs.ovf_slots + 2 * kDeferCapMin);
+        if (per_block_min == 0 || fs.fixed_words < per_block_min) return hipErrorInvalidValue;
+        const size_t fit_blocks = fs.fixed_words / per_block_min;
+        if (grid > fit_blocks) grid = static_cast<unsigned>(fit_blocks);
+        const size_t thr = static_cast<size_t>(grid) * kBlock;
+        const size_t per_thr = fs.fixed_words / thr;
+        const size_t cap = (per_thr - fs.ovf_slots) / 2;
+        f.defer_cap = static_cast<int>(cap < static_cast<size_t>(kDeferCap) ? cap : kDeferCap);
+        f.dbuf = f.ovf + thr * fs.ovf_slots;
+        if (fs.ovf_slots == 0) f.ovf = nullptr;
+    }
+    k_trace<K, FM, BVH, CM, CT><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, f);
     return hipGetLastError();
 }
 
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__
     Stack st{as_lds(lds_stack), as_glb(fs.ovf_slots > 0 ? fs.ovf + gtid : nullptr), static_cast<int>(nthr),
              static_cast<int>(threadIdx.x), 0, kStackLds};
     const PackedSource src{scenes, items, n_items, n_rays};
-    Deferred dq{as_glb(fs.dbuf + gtid * 2 * kDeferCap), kDeferCap, 0, 0, 0, 0};
+    Deferred dq{as_glb(fs.dbuf + gtid * 2 * fs.defer_cap), fs.defer_cap, 0, 0, 0, 0};
     trace_flat<K, FM, kColPlain, CT>(src, fs.next_ray, P, st, dq);
 }
 

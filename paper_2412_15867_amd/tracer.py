@@ -245,6 +245,25 @@ def trace(scene: Scene, ro: torch.Tensor, rd: torch.Tensor, cfg: Optional[TraceC
     return res
 
 
+def trace_noalloc(scene: Scene, ro: torch.Tensor, rd: torch.Tensor, out: TraceResult,
+                  cfg: Optional[TraceConfig] = None, **kw) -> TraceResult:
+    """`trace` into caller-allocated outputs through irgs_trace_noalloc: the
+    library allocates nothing (its scratch is a fixed per-device array), so
+    the call can sit inside HIP graph capture or an allocation-free loop.
+    Calls that overlap on one GPU share that array and race."""
+    cfg = cfg or TraceConfig(**kw)
+    if cfg.sort_rays:
+        raise ValueError("sort_rays needs a per-ray workspace: use trace()")
+    R = _rays(scene, ro, rd)
+    flags = (_lib.FLAG_BRUTE_FORCE if cfg.brute_force else 0) | cfg.flags()
+    p = scene.params(cfg, flags)
+    o = out.out_struct()
+    with torch.cuda.device(scene.device):
+        check(_lib.lib().irgs_trace_noalloc(scene.handle, ctypes.byref(p), R, _ptr(ro), _ptr(rd), ctypes.byref(o),
+                                            _stream_handle(scene.device)), "irgs_trace_noalloc")
+    return out
+
+
 def trace_backward(scene: Scene, ro, rd, saved: TraceResult, g_opacity=None, g_feat=None, g_depth=None,
                    cfg: Optional[TraceConfig] = None, grads: Optional[dict] = None, **kw) -> dict:
     """Accumulate dL/d(mu, quat, scale, opacity, feat) for upstream gradients
