@@ -439,7 +439,7 @@ def run_serve(args):
     rate = args.load * cap / mean_rays
     arrivals = synth.poisson_arrivals(n_req, rate)
     log(f"capacity {cap / 1e6:.1f} Mrays/s, {n_req} requests, mean {mean_rays:.0f} rays, rate {rate:.1f}/s")
-    srv = Server(scenes, cfg)
+    srv = Server(scenes, cfg, chunk_rays=args.chunk_rays, max_launch_rays=args.launch_rays)
     reqs = run_open_loop(srv, arrivals, make)
     torch.cuda.synchronize()
     packed = latency_stats(reqs)
@@ -458,8 +458,10 @@ def run_serve(args):
             "ms_per_step": round(packed["mean_ms"], 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"3 resident scenes {sizes} surfels, {n_req} Poisson requests, rays "
-                                   f"log-uniform [1e3, {P}], offered load {args.load} of packed capacity, k={args.k}"},
+                                   f"log-uniform [1e3, {P}], offered load {args.load} of packed capacity, k={args.k}, "
+                                   f"work items of {args.chunk_rays} rays, launches of up to {args.launch_rays}"},
             "packed": packed, "per_request": base, "launches": srv.launches,
+            "launches_per_request": round(float(np.mean([r.launches for r in reqs])), 3),
             "capacity_mrays_s": round(cap / 1e6, 3), "mix_equals_alone": same}
     for s in scenes:
         s.close()
@@ -699,6 +701,8 @@ def main():
                     help="relight workload: directions drawn by the sky's intensity or stratified")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--chunk-rays", type=int, default=65536, help="serve: rays per work item")
+    ap.add_argument("--launch-rays", type=int, default=1 << 21, help="serve: rays per packed launch at most")
     ap.add_argument("--surfels", type=int, default=1_000_000)
     ap.add_argument("--points", type=int, default=256 * 256)
     ap.add_argument("--dirs", type=int, default=64)

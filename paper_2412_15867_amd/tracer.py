@@ -339,7 +339,10 @@ class TraceFn(torch.autograd.Function):
 def trace_packed(scenes: Sequence[Scene], items: Sequence[tuple], cfg: Optional[TraceConfig] = None, **kw):
     """One persistent launch over several requests.  Each item is
     (scene_index, ro, rd, result) with ro/rd (R_i, 3) and result a
-    TraceResult allocated for R_i rays and that scene's F."""
+    TraceResult allocated for R_i rays and that scene's F; or
+    (scene_index, ro, rd, result, begin, count): only rays
+    [begin, begin + count) of the request, written at the same indices of
+    its result."""
     cfg = cfg or TraceConfig(**kw)
     if not scenes:
         raise ValueError("no scenes")
@@ -351,13 +354,19 @@ def trace_packed(scenes: Sequence[Scene], items: Sequence[tuple], cfg: Optional[
                     float(cfg.t_max), scenes[0].support_sigma, 0, 0)
     handles = (ctypes.c_void_p * len(scenes))(*[s.handle.value for s in scenes])
     works = (_lib.Work * max(len(items), 1))()
-    for i, (si, ro, rd, res) in enumerate(items):
+    for i, it in enumerate(items):
+        si, ro, rd, res = it[:4]
         R = ro.shape[0]
+        begin, count = (int(it[4]), int(it[5])) if len(it) > 4 else (0, R)
         _req(ro, "ro", (R, 3), device=dev)
         _req(rd, "rd", (R, 3), device=dev)
+        if begin < 0 or count < 0 or begin + count > R:
+            raise ValueError(f"item {i}: rays [{begin}, {begin + count}) outside [0, {R})")
+        if res.opacity.shape[0] != R:
+            raise ValueError(f"item {i}: result holds {res.opacity.shape[0]} rays, the request {R}")
         works[i].scene = int(si)
-        works[i].ray_begin = 0
-        works[i].ray_count = R
+        works[i].ray_begin = begin
+        works[i].ray_count = count
         works[i].ro = ro.data_ptr()
         works[i].rd = rd.data_ptr()
         works[i].out = res.out_struct()
