@@ -204,15 +204,20 @@ irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, 
  * must be refit or rebuilt before the next trace). */
 irgs_status irgs_scene_set_params(irgs_scene scene, const irgs_surfels* params);
 
-/* Build: per-surfel records and support boxes, Morton codes, radix sort,
+/* Build (Sec. 3.2: the surfels are wrapped in bounding proxies of their
+ * alpha_min support, Eq. 5, and organised in a BVH that the ray tracer
+ * traverses; here each proxy is the exact box of the support ellipse):
+ * per-surfel records and support boxes, Morton codes, radix sort,
  * hierarchy (PLOC, or the radix tree with IRGS_FLAG_RADIX_TREE), level-by-level
  * boxes, the 4-wide collapse.  Allocates the scene's device buffers on first
  * use.  Uses params->alpha_min, support_sigma, leaf_size and that flag.
  * Reads level sizes and the tree depth back (synchronises `stream`). */
 irgs_status irgs_scene_build(irgs_scene scene, const irgs_params* params, void* stream);
 
-/* Refit after the parameters changed in place: records, leaf boxes and
- * internal boxes recomputed, tree topology kept.  Asynchronous. */
+/* Refit after the parameters changed in place (Sec. 4, implementation
+ * details: the BVH is updated at every training iteration, because the
+ * surfels move): records, leaf boxes and internal boxes recomputed, tree
+ * topology kept.  Asynchronous. */
 irgs_status irgs_scene_refit(irgs_scene scene, void* stream);
 
 /* Forward trace of R rays, ro and rd (R x 3, directions need not be unit:
@@ -240,7 +245,10 @@ irgs_status irgs_trace(irgs_scene scene, const irgs_params* params, int64_t R, c
 irgs_status irgs_trace_noalloc(irgs_scene scene, const irgs_params* params, int64_t R, const float* ro,
                                const float* rd, const irgs_out* out, void* stream);
 
-/* Backward of irgs_trace over the same rays: accumulates parameter
+/* Backward of irgs_trace over the same rays (Sec. 3.3, Stage II: the
+ * indirect radiance and visibility returned by the trace are differentiated
+ * with respect to the surfels every iteration; the "detach indirect"
+ * ablation of Sec. 4.2 turns exactly this off): accumulates parameter
  * gradients.  `saved` is the irgs_out of the forward call: n_hits is
  * required; with hit_ids and hit_T present (and IRGS_FLAG_RECOMPUTE unset)
  * rays with n_hits <= H_cap replay their saved hits, every other ray

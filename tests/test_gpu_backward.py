@@ -221,19 +221,47 @@ def test_autograd_function_matches_direct_backward(cube):
     scene.close()
 
 
+@pytest.mark.parametrize("recompute", [False, True])
+def test_autograd_function_matches_fp64_oracle(cube, recompute):
+    """The autograd wrapper with plain features (RGB) against the FP64
+    gradient oracle over the same, validated hit lists: dL/d(mu, q, s, o, f)
+    for L = sum(gO O + gF . F + gD D)."""
+    from paper_2412_15867_amd import Scene, TraceConfig, TraceFn, trace
+    sc, ro, rd, gO, gF, gD = cube
+    note(f"TraceFn vs oracle recompute={recompute}")
+    params = [dev(x).requires_grad_(True) for x in sc.astuple()]
+    scene = Scene(*[p.detach() for p in params])
+    scene.set_params(*params)
+    cfg = TraceConfig(k=16, recompute=recompute)
+    O, F, D = TraceFn.apply(*params, dev(ro), dev(rd), scene, cfg)
+    loss = (O * dev(gO)).sum() + (F * dev(gF)).sum() + (D * dev(gD)).sum()
+    loss.backward()
+    fwd = to_np(trace(scene, dev(ro), dev(rd), cfg, hit_cap=256))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(O.detach().cpu().numpy(), fwd["O"])
+    validate(sc.astuple(), ro, rd, fwd)
+    ref = ograd.grad_given_hits(sc.astuple(), ro, rd, lists_of(fwd), gO, gF, gD)
+    got = {name: p.grad.detach().cpu().numpy().astype(np.float64)
+           for p, name in zip(params, ("mu", "quat", "scale", "opacity", "feat"))}
+    w = grad_close(got, ref)
+    note(f"TraceFn worst rel err {w}")
+    scene.close()
+
+
 def test_full_size_headline_config_sampled():
     """The benchmarked configuration at full size -- 1M surfels, 256x256x64 =
     4,194,304 MC rays, k = 16, one launch each way -- with the forward
-    validated on 384 sampled rays and the backward checked against the FP64
-    oracle with upstream gradients non-zero only on 2,048 sampled rays; the
-    backward also without stored lists (the rays traced again in three
-    equal batches)."""
+    validated on 4,096 sampled rays and the backward checked against the FP64
+    oracle with upstream gradients non-zero only on 4,096 other sampled rays,
+    whose hit lists are validated too (the gradient oracle differentiates
+    along the GPU's lists, so those lists must be right); the backward also
+    without stored lists (the rays traced again in three equal batches)."""
     from paper_2412_15867_amd import TraceConfig, trace, trace_backward
     lay = synth.layout()
     sc = synth.surface_scene(1_000_000, F=8, lay=lay)
     ro, rd = synth.mc_rays(256 * 256, 64, lay=lay)
     R = ro.shape[0]
-    gO, gF, gD, idx = synth.upstream(R, 8, mask_rays=2048)
+    gO, gF, gD, idx = synth.upstream(R, 8, mask_rays=4096)
     note("full size forward + backward")
     scene = make_scene(sc)
     cfg = TraceConfig(k=16)
@@ -248,9 +276,11 @@ def test_full_size_headline_config_sampled():
     g_re = {k: v.cpu().numpy().astype(np.float64) for k, v in grads_re.items()}
     scene.close()
     assert fwd["n_hits"].max() <= 256
-    sample = np.sort(np.random.default_rng(50).choice(R, 384, replace=False))
-    note("validating sampled rays")
+    sample = np.sort(np.random.default_rng(50).choice(R, 4096, replace=False))
+    note("validating 4,096 sampled rays")
     validate(sc.astuple(), ro, rd, fwd, rays=sample)
+    note("validating the 4,096 masked rays")
+    validate(sc.astuple(), ro, rd, fwd, rays=idx)
     # gradient: only the masked rays contribute; the oracle differentiates them
     note("oracle gradient on the masked rays")
     lists = lists_of({"hit_ids": fwd["hit_ids"][idx], "n_hits": fwd["n_hits"][idx]})

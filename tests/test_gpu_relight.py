@@ -24,6 +24,53 @@ def material_cube():
     return synth.Surfels(sc.mu, sc.quat, sc.scale, sc.opac, feat.astype(F32))
 
 
+def _texel_decision(d, E):
+    """(face, row, col) of the nearest texel of each direction (FP64), and
+    the distance of each choice to its nearest boundary: the gap between the
+    largest and second-largest |component| relative to the largest (face),
+    and the distance of (s + 1) E / 2, (t + 1) E / 2 to the nearest interior
+    integer (row, col), in texel units."""
+    from oracle.shade import cube_texel
+    d = np.asarray(d, np.float64)
+    f, row, col = cube_texel(d, E, np.float64)
+    ax = np.sort(np.abs(d), axis=-1)
+    m_face = (ax[:, 2] - ax[:, 1]) / np.maximum(ax[:, 2], 1e-300)
+    major = np.argmax(np.abs(d), -1)
+    m = np.take_along_axis(np.abs(d), major[:, None], -1)[:, 0]
+    s = np.select([f == 0, f == 1, f == 2, f == 3, f == 4, f == 5],
+                  [-d[:, 2], d[:, 2], d[:, 0], d[:, 0], d[:, 0], -d[:, 0]]) / np.maximum(m, 1e-300)
+    t = np.select([f == 0, f == 1, f == 2, f == 3, f == 4, f == 5],
+                  [-d[:, 1], -d[:, 1], d[:, 2], -d[:, 2], -d[:, 1], -d[:, 1]]) / np.maximum(m, 1e-300)
+    def frac_gap(x, hi):
+        k = np.clip(np.round(x), 1, hi - 1)
+        return np.abs(x - k) if hi > 1 else np.full_like(x, np.inf)
+    return np.stack([f, row, col], 1), np.minimum(m_face, np.minimum(frac_gap((s + 1) * E / 2, E),
+                                                                     frac_gap((t + 1) * E / 2, E)))
+
+
+def lookup_decisions(O, Fo, rd, E, M, S):
+    """Every integer decision of the split-sum lookup of each ray (texel of
+    the blended normal, texel of the mirror direction, prefiltered level,
+    BRDF-table cell), taken in FP64 from trace outputs, and the smallest
+    distance of any of them to a boundary (rays without a hit: +inf)."""
+    O = np.asarray(O, np.float64)
+    rd = np.asarray(rd, np.float64)
+    rd = rd / np.linalg.norm(rd, axis=-1, keepdims=True)
+    feat, N = orl.blend(O, Fo, 4)
+    hit = O > 0
+    N = np.where(hit[:, None], N, np.array([0.0, 0.0, 1.0]))
+    Rg = np.clip(feat[:, 3], 0.0, 1.0)
+    nv = np.clip((N * -rd).sum(-1), 0.0, 1.0)
+    refl = rd - 2.0 * (rd * N).sum(-1, keepdims=True) * N
+    dn, mn = _texel_decision(N, E)
+    dr, mr = _texel_decision(refl, E)
+    lev_x, i_x, j_x = Rg * M + 0.5, nv * S, Rg * S
+    dec = np.concatenate([dn, dr, np.stack([np.floor(lev_x), np.floor(i_x), np.floor(j_x)], 1)], 1)
+    gap = lambda x: np.abs(x - np.round(x))
+    margin = np.minimum.reduce([mn, mr, gap(lev_x), gap(i_x), gap(j_x)])
+    return np.where(hit[:, None], dec, -1), np.where(hit, margin, np.inf)
+
+
 def test_prefilter_and_table_match_oracle():
     from paper_2412_15867_amd import brdf_table, env_prefilter
     E, M, S = 8, 4, 16
@@ -83,11 +130,25 @@ def test_relight_lind_matches_oracle():
     want = orl.relight_lind(rep["O"], rep["F"], rd, orl.irradiance(env), orl.prefilter(env, M), orl.brdf_table(S))
     assert np.all(np.isfinite(lind))
     np.testing.assert_array_equal(lind[fwd["O"] == 0], 0)
-    # the nearest texel / level / cell is an integer decided by floating point
-    # from the normalised blend: allow the rare ray whose FP32 decision lands
-    # on the other side of a boundary
-    ok = np.all(np.abs(lind - want) <= 2e-4 * (1 + np.abs(want)), axis=1)
-    assert ok.mean() > 0.995, ok.mean()
+    # The nearest texel, level and cell are integers decided by floating
+    # point from the normalised blend.  Split the check: (1) the lookups, on
+    # the GPU's own (validated) trace outputs: every ray equals the oracle
+    # shading those outputs, except a ray one of whose decisions lies within
+    # FP32 rounding of a boundary; (2) against the FP64 replay: every ray
+    # whose decisions are the same from the GPU outputs and from the replay
+    # agrees within the replay tolerance carried through the blend (1e-4 on
+    # O and F, divided by O).
+    own = orl.relight_lind(fwd["O"], fwd["F"], rd, orl.irradiance(env), orl.prefilter(env, M), orl.brdf_table(S))
+    d_gpu, m_gpu = lookup_decisions(fwd["O"], fwd["F"], rd, E, M, S)
+    d_rep, _ = lookup_decisions(rep["O"], rep["F"], rd, E, M, S)
+    bad = ~np.all(np.abs(lind - own) <= 2e-5 * (1 + np.abs(own)), axis=1)
+    assert np.all(m_gpu[bad] < 1e-4), (np.nonzero(bad & (m_gpu >= 1e-4))[0][:5], m_gpu[bad].max())
+    same = np.all(d_gpu == d_rep, axis=1) & (fwd["O"] > 0)
+    O = np.maximum(fwd["O"], 1e-30)[:, None]
+    ok = np.abs(lind - want) <= 2e-4 * (1 + np.abs(want)) * (1 + 1 / O)
+    assert np.all(ok[same]), np.nonzero(~np.all(ok, axis=1) & same)[0][:5]
+    note(f"relight lind: {bad.sum()} boundary rays, {(~same & (fwd['O'] > 0)).sum()} decided differently "
+         f"from the replay, of {len(lind)}")
 
 
 def test_env_cdf_matches_oracle():
