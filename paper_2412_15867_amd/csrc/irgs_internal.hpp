@@ -108,6 +108,9 @@ inline unsigned persistent_grid(int64_t max_blocks, int64_t resident)
 // Device scratch of a persistent forward launch, sized for trace_threads(R)
 // threads (the launch may use fewer).
 constexpr int kDeferCap = 192;
+// Deferred-list entries a lane stages in LDS before writing them as one
+// group (kDeferCap and every fitted list size are multiples of it).
+constexpr int kDeferStage = 8;
 // Smallest deferred-list half a launch into a fixed scratch area takes
 // before it gives up resident blocks instead.
 constexpr int kDeferCapMin = 32;
@@ -129,9 +132,13 @@ struct FlatScratch {
 // True when a launch into a fixed area of `words` ints can run at least one
 // block (its threads' stack overflow and deferred-list halves of
 // kDeferCapMin entries).
+inline size_t fixed_scratch_block_words(int ovf_slots, int block)
+{
+    return static_cast<size_t>(block) * (ovf_slots + 2 * kDeferCapMin) + kDeferStage;  // + alignment of dbuf
+}
 inline bool fixed_scratch_fits(size_t words, int ovf_slots, int block)
 {
-    return words >= static_cast<size_t>(block) * (ovf_slots + 2 * kDeferCapMin);
+    return words >= fixed_scratch_block_words(ovf_slots, block);
 }
 
 // Claim order of a forward trace: rays sorted by the Morton code of their

@@ -189,32 +189,74 @@ __device__ __forceinline__ void add_features(const SceneView& sc, const TracePar
 // after the round's last key lies in exactly one of them, so the next round
 // starts from this list instead of the root.  Two halves (this round's input,
 // next round's output); an overflowing output falls back to a root restart.
+//
+// A lane's puts are spread over many iterations, long enough for L2 to evict
+// a line between two of them, so single 4-byte stores would each write a
+// partial line back.  Puts are therefore staged in an LDS ring of
+// 2 kDeferStage entries per lane (slot-major, so a wave's writes fall in
+// distinct banks) and written back kDeferStage at a time (32 bytes, one
+// after the other, so L2 holds the whole group in one line) by one flush
+// step at the top of each iteration; the round's end writes the rest.  An
+// iteration puts at most 5 entries (4 children, or 2 hits, plus 1 pushed out
+// of the buffer) and each flush step retires a full group, so at most 12
+// entries are ever staged and the ring never overwrites one that is waiting.
+// With kStaged false (the k = 32 and 64 instances, whose rounds defer half
+// as much or less and which measured slower with the staging) each put is
+// a direct store.
+constexpr int kDeferRing = 2 * kDeferStage;
+
+template <bool kStaged>
 struct Deferred {
-    glb_int* base;  // 2 * cap entries of this lane
+    glb_int* base;   // 2 * cap entries of this lane (cap a multiple of kDeferStage)
+    lds_int* stage;  // this lane's ring slots: stage[g * kBlock], g < kDeferRing (staged lists)
     int cap;
-    int half;       // half holding this round's input
+    int half;        // half holding this round's input
     int n_in, i_in, n_out;
+    int flushed;     // output entries written back (a multiple of kDeferStage; staged lists)
 
     __device__ __forceinline__ void reset()
     {
         half = 0;
-        n_in = i_in = n_out = 0;
+        n_in = i_in = n_out = flushed = 0;
     }
     __device__ __forceinline__ void put(int item)
     {
-        if (n_out < cap) base[(half ^ 1) * cap + n_out] = item;
+        if (n_out < cap) {
+            if constexpr (kStaged)
+                stage[(n_out & (kDeferRing - 1)) * kBlock] = item;
+            else
+                base[(half ^ 1) * cap + n_out] = item;
+        }
         ++n_out;
+    }
+    // A full group waits (an overflowing list is dropped whole: nothing to write).
+    __device__ __forceinline__ bool group_ready() const
+    {
+        return kStaged && n_out <= cap && n_out - flushed >= kDeferStage;
+    }
+    __device__ __forceinline__ void flush_group()
+    {
+        glb_int* dst = base + (half ^ 1) * cap + flushed;
+        const int s0 = flushed & (kDeferRing - 1);
+#pragma unroll
+        for (int g = 0; g < kDeferStage; ++g) dst[g] = stage[(s0 + g) * kBlock];
+        flushed += kDeferStage;
     }
     __device__ __forceinline__ int take() { return base[half * cap + i_in++]; }
     __device__ __forceinline__ bool has() const { return i_in < n_in; }
-    // Next round: consume what this one deferred; false = it overflowed.
+    // Next round: consume what this one deferred; false = it overflowed.  The
+    // staged rest is written first, a partly filled last group whole
+    // (entries past n_out are never read; flushed + kDeferStage <= cap).
     __device__ __forceinline__ bool flip()
     {
         const bool ok = n_out <= cap;
+        if (kStaged && ok)
+            while (flushed < n_out) flush_group();
         half ^= 1;
         n_in = ok ? n_out : 0;
         i_in = 0;
         n_out = 0;
+        flushed = 0;
         return ok;
     }
 };
@@ -223,7 +265,7 @@ struct Deferred {
 // their registers stay free.
 template <int K, int FM, int CM, bool CT, class Source>
 __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long* next_ray, const TraceParams& P,
-                                           Stack& st, Deferred dq)
+                                           Stack& st, Deferred<(K <= 16)> dq)
 {
     enum { kTrav = 0, kComp = 1, kFetch = 2, kDead = 3, kIns = 4 };
     const float inf = __int_as_float(0x7f800000);
@@ -263,6 +305,14 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 if (ev != kKeyNone) dq.put(cluster_ref(key_pos(ev), 1));  // pushed out of the buffer
                 pend = kKeyNone;
                 mode = kTrav;
+            }
+        }
+        // Staged deferred entries: write a full group back (wave-uniform
+        // branch, at the point of the loop with the fewest live registers).
+        if constexpr (K <= 16) {
+            const bool want_flush = dq.group_ready();
+            if (__ballot(want_flush)) {
+                if (want_flush) dq.flush_group();
             }
         }
         // Phase vote: the wave runs, per iteration, only the kind of step the

@@ -94,13 +94,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K <= 16 
                                                   OutPtrs out, FlatScratch fs)
 {
     __shared__ int lds_stack[BVH ? kStackLds * kBlock : 1];
+    __shared__ int lds_stage[BVH && K <= 16 ? kDeferRing * kBlock : 1];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
     Stack st{as_lds(lds_stack), as_glb(fs.ovf_slots > 0 ? fs.ovf + gtid : nullptr), static_cast<int>(nthr),
              static_cast<int>(threadIdx.x), 0, kStackLds};
     if (BVH) {
         const PlainSource src{sc, out, ro, rd, R, fs.order};
-        Deferred dq{as_glb(fs.dbuf + gtid * 2 * fs.defer_cap), fs.defer_cap, 0, 0, 0, 0};
+        Deferred<(K <= 16)> dq{as_glb(fs.dbuf + gtid * 2 * fs.defer_cap), as_lds(lds_stage) + threadIdx.x, fs.defer_cap, 0, 0, 0, 0, 0};
         trace_flat<K, FM, CM, CT>(src, fs.next_ray, P, st, dq);
     } else {
         for (int64_t r = gtid; r < R; r += nthr) {
@@ -124,15 +125,17 @@ hipError_t launch_kct(const SceneView& sc, const TraceParams& P, int64_t R, cons
         // One fixed area: the stack overflow of every thread, then the
         // deferred lists.  Keep every resident block while a half of at
         // least kDeferCapMin entries fits, else drop blocks.
-        const size_t per_block_min = static_cast<size_t>(kBlock) * (fs.ovf_slots + 2 * kDeferCapMin);
-        if (per_block_min == 0 || fs.fixed_words < per_block_min) return hipErrorInvalidValue;
+        // (the lists start 32-byte aligned and hold whole staged groups)
+        const size_t per_block_min = fixed_scratch_block_words(fs.ovf_slots, kBlock);
+        if (fs.fixed_words < per_block_min) return hipErrorInvalidValue;
         const size_t fit_blocks = fs.fixed_words / per_block_min;
         if (grid > fit_blocks) grid = static_cast<unsigned>(fit_blocks);
         const size_t thr = static_cast<size_t>(grid) * kBlock;
-        const size_t per_thr = fs.fixed_words / thr;
-        const size_t cap = (per_thr - fs.ovf_slots) / 2;
+        const size_t ovf_words = (thr * fs.ovf_slots + kDeferStage - 1) / kDeferStage * kDeferStage;
+        size_t cap = (fs.fixed_words - ovf_words) / thr / 2;
+        cap = cap / kDeferStage * kDeferStage;
         f.defer_cap = static_cast<int>(cap < static_cast<size_t>(kDeferCap) ? cap : kDeferCap);
-        f.dbuf = f.ovf + thr * fs.ovf_slots;
+        f.dbuf = f.ovf + ovf_words;
         if (fs.ovf_slots == 0) f.ovf = nullptr;
     }
     k_trace<K, FM, BVH, CM, CT><<<grid, kBlock, 0, st>>>(sc, P, R, ro, rd, out, f);
@@ -192,17 +195,18 @@ hipError_t launch_b(const SceneView& sc, const TraceParams& P, int k, int64_t R,
 // work item's rays (an item is one request on one scene), so different
 // requests and scenes share one launch.
 template <int K, int FM, bool CT>
-__global__ __launch_bounds__(kBlock) void k_packed(const SceneView* __restrict__ scenes,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(K == 32 && FM <= 8 ? 3 : 1))) void k_packed(const SceneView* __restrict__ scenes,
                                                    const WorkItem* __restrict__ items, int n_items,
                                                    int64_t n_rays, TraceParams P, FlatScratch fs)
 {
     __shared__ int lds_stack[kStackLds * kBlock];
+    __shared__ int lds_stage[K <= 16 ? kDeferRing * kBlock : 1];
     const int64_t gtid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
     Stack st{as_lds(lds_stack), as_glb(fs.ovf_slots > 0 ? fs.ovf + gtid : nullptr), static_cast<int>(nthr),
              static_cast<int>(threadIdx.x), 0, kStackLds};
     const PackedSource src{scenes, items, n_items, n_rays};
-    Deferred dq{as_glb(fs.dbuf + gtid * 2 * fs.defer_cap), fs.defer_cap, 0, 0, 0, 0};
+    Deferred<(K <= 16)> dq{as_glb(fs.dbuf + gtid * 2 * fs.defer_cap), as_lds(lds_stage) + threadIdx.x, fs.defer_cap, 0, 0, 0, 0, 0};
     trace_flat<K, FM, kColPlain, CT>(src, fs.next_ray, P, st, dq);
 }
 
