@@ -429,7 +429,7 @@ size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
         const size_t per_ray = static_cast<size_t>(kRetraceCap) * 8 + (3 + fo) * sizeof(float);
         const int64_t bmax = std::max<int64_t>(1, static_cast<int64_t>(kRetraceBytes / per_ray));
         const int64_t nb = (R + bmax - 1) / bmax;
-        b += static_cast<size_t>((R + nb - 1) / nb) * per_ray + thr * kBwdCheckpoints * 4 * sizeof(float);
+        b += static_cast<size_t>((R + nb - 1) / nb) * per_ray + remarch_words(R) * sizeof(float);
     }
     return b;  // plus, for a backward, 4 * ceil32(10 + F) bytes per surfel
 }

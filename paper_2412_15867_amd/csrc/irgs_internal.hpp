@@ -154,10 +154,26 @@ hipError_t launch_trace(const SceneView& sc, const TraceParams& P, int k, bool u
 
 // Backward.  Store mode reads saved ids and T (rays with n_hits > H_cap are
 // re-marched); recompute mode re-marches every ray.  `ck` is scratch of
-// backward_scratch_words(R, N, F) floats: re-march checkpoints, the
-// interleaved per-surfel gradient accumulator, then a chunk-claim counter.
-constexpr int kBwdCheckpoints = 8;
+// backward_scratch_words(R, N, F) floats: the re-march lanes' checkpoints and
+// private hit lists, the interleaved per-surfel gradient accumulator, then a
+// chunk-claim counter.
+constexpr int kBwdCheckpoints = 16;
 constexpr int kBwdClaimWords = 64;
+// Re-march lanes keep each ray's first kRemarchList hits (id and
+// transmittance) in a private list and walk it back to front; the re-march
+// launch uses at most kRemarchThreads lanes, which sizes those lists.
+constexpr int kRemarchList = 512;
+constexpr int64_t kRemarchThreads = 131072;
+inline int64_t remarch_threads(int64_t R)
+{
+    const int64_t t = trace_threads(R);
+    return t < kRemarchThreads ? t : kRemarchThreads;
+}
+// floats of the re-march area: checkpoints (4 per entry), then ids and T
+inline size_t remarch_words(int64_t R)
+{
+    return static_cast<size_t>(remarch_threads(R)) * (kBwdCheckpoints * 4 + 2 * kRemarchList);
+}
 inline int grad_stride(int F) { return ((10 + F + 31) / 32) * 32; }
 size_t sort_pairs_count_bytes(int n);
 hipError_t sort_pairs(int n, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint32_t* counts, int passes,
@@ -175,8 +191,8 @@ inline size_t backward_scratch_words(int64_t R, int64_t N, int F)
 {
     // the ray order is used only for gradients wider than the LDS table (the
     // backward sorts exactly when F > 8: keep the two conditions the same)
-    return static_cast<size_t>(trace_threads(R)) * kBwdCheckpoints * 4 + static_cast<size_t>(N) * grad_stride(F) +
-           kBwdClaimWords + (F > 8 ? ray_sort_words(R) : 0);
+    return remarch_words(R) + static_cast<size_t>(N) * grad_stride(F) + kBwdClaimWords +
+           (F > 8 ? ray_sort_words(R) : 0);
 }
 hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int k, int64_t R,
                            const float* ro, const float* rd, const OutPtrs& saved, bool use_saved,

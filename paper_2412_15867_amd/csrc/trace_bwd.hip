@@ -273,13 +273,21 @@ __device__ __forceinline__ LaneUp<FU> load_upstream(const GradIn& gin, int64_t r
     return u;
 }
 
-// Re-march one ray (no saved list, or more hits than were saved): pass 1
-// records the state at the start of each round, pass 2 re-collects the
-// rounds last to first and walks each back to front.
+// Re-march one ray (no saved list, or more hits than were saved).  Pass 1
+// marches the k-buffer rounds again (the forward's arithmetic, so T is
+// reproduced bit for bit), recording each composited hit (id and the
+// transmittance before it) in the lane's private list while it fits, and
+// the state at the start of rounds as checkpoints.  Pass 2 walks the
+// private list back to front or, for a ray longer than the list,
+// re-collects the rounds last to first from the nearest checkpoint.
+// Checkpoints are kept for every stride-th round: once all kBwdCheckpoints
+// are taken every other one is dropped and the stride doubles, so pass 2
+// re-collects at most stride - 1 extra rounds per round (instead of
+// re-marching from the last checkpoint for every round past them).
 template <int K, int FM, int FU, bool SH>
 __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
                                             const Ray& ray, const LaneUp<FU>& up, const GradAcc& acc, Stack& st,
-                                            float4* ck, int64_t ck_stride)
+                                            float4* ck, int64_t ck_stride, int* pid, float* pT)
 {
     float S = 0.0f;
     Counters ct;
@@ -288,18 +296,33 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
     float T = 1.0f;
     int nh = 0;
     int rounds = 0;
+    int stride = 1;  // a power of two: checkpoint i holds the start of round i * stride
+    int nck = 0;
     bool done = false;
     while (!done) {
-        if (rounds < kBwdCheckpoints)
-            ck[rounds * ck_stride] = make_float4(__uint_as_float(static_cast<uint32_t>(after >> 32)),
-                                                 __uint_as_float(static_cast<uint32_t>(after)), T, __int_as_float(nh));
+        if ((rounds & (stride - 1)) == 0) {
+            if (nck == kBwdCheckpoints) {
+                for (int i = 1; i < kBwdCheckpoints / 2; ++i) ck[i * ck_stride] = ck[2 * i * ck_stride];
+                nck = kBwdCheckpoints / 2;
+                stride *= 2;
+            }
+            if ((rounds & (stride - 1)) == 0)
+                ck[(nck++) * ck_stride] = make_float4(__uint_as_float(static_cast<uint32_t>(after >> 32)),
+                                                      __uint_as_float(static_cast<uint32_t>(after)), T,
+                                                      __int_as_float(nh));
+        }
         KBuf<K> kb;
         kb.clear();
         collect_bvh<K>(kb, sc, ray, q, P.t_min, P.t_max, after, st, ct);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < kb.cnt && !done) {
-                T = T * (1.0f - entry_alpha(sc, ray, kb.pos(j)));
+                const int pos = kb.pos(j);
+                if (nh < kRemarchList) {
+                    pid[nh] = __float_as_int(sc.rec[pos].c.w);
+                    pT[nh] = T;
+                }
+                T = T * (1.0f - entry_alpha(sc, ray, pos));
                 ++nh;
                 if (T < P.T_min) done = true;
             }
@@ -311,14 +334,23 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
         ++rounds;
     }
     const int total = nh;
+    if (total <= kRemarchList) {
+        for (int h = total - 1; h >= 0; --h) {
+            const int id = pid[h];
+            HitGrad<FM> hg;
+            grad_hit<FM, FU, SH>(raw, P, id, ray, pT[h], S, up.gO, up.gF, up.gD, hg);
+            acc.direct<FM>(id, hg);
+        }
+        return;
+    }
     for (int rr = rounds - 1; rr >= 0; --rr) {
-        const int base = rr < kBwdCheckpoints ? rr : kBwdCheckpoints - 1;
+        const int base = rr / stride;
         float4 c4 = ck[base * ck_stride];
         after = (static_cast<uint64_t>(__float_as_uint(c4.x)) << 32) | __float_as_uint(c4.y);
         T = c4.z;
         int nb = __float_as_int(c4.w);
         KBuf<K> kb;
-        for (int adv = base; adv < rr; ++adv) {  // rounds past the last checkpoint
+        for (int adv = base * stride; adv < rr; ++adv) {  // rounds between the checkpoint and rr
             kb.clear();
             collect_bvh<K>(kb, sc, ray, q, P.t_min, P.t_max, after, st, ct);
 #pragma unroll
@@ -361,7 +393,7 @@ __global__ __launch_bounds__(kBwdBlock) __attribute__((amdgpu_waves_per_eu(!RM &
 void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                         const float* __restrict__ ro, const float* __restrict__ rd,
                                                         OutPtrs saved, bool use_saved, GradIn gin, float* gbuf,
-                                                        int gs, int* ovf, int ovf_slots, float4* ck,
+                                                        int gs, int* ovf, int ovf_slots, float4* ck, int* plist,
                                                         unsigned long long* next_chunk,
                                                         const uint32_t* __restrict__ order)
 {
@@ -380,7 +412,11 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
     const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBwdBlock;
     // the re-march stack lives entirely in the global area (0 LDS slots)
     Stack st{nullptr, as_glb(ovf_slots > 0 ? ovf + gtid : nullptr), static_cast<int>(nthr), tid, 0, 0};
-    float4* myck = ck ? ck + gtid : nullptr;
+    // re-march lanes (gtid < kRemarchThreads): checkpoints slot-major, the
+    // private list contiguous per lane (ids, then T)
+    float4* myck = RM ? ck + gtid : nullptr;
+    int* my_ids = RM ? plist + gtid * (2 * kRemarchList) : nullptr;
+    float* my_T = RM ? reinterpret_cast<float*>(my_ids + kRemarchList) : nullptr;
     const GradAcc acc{hkeys, hvals, &hfilled, gbuf, gs, P.F};
     const int nc = 10 + P.F;
     const int64_t chunks = (R + kBwdBlock - 1) / kBwdBlock;
@@ -411,7 +447,7 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                         stored = true;
                         nh = nh_saved;
                     } else {
-                        bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr);
+                        bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr, my_ids, my_T);
                     }
                 }
             }
@@ -511,8 +547,10 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
                      int* ovf, int ovf_slots, float* ck, hipStream_t st)
 {
     const int64_t nthr = trace_threads(R);
+    const int64_t rm_thr = remarch_threads(R);
     const int gs = grad_stride(P.F);
-    float* gbuf = ck + static_cast<size_t>(nthr) * kBwdCheckpoints * 4;
+    int* plist = reinterpret_cast<int*>(ck + static_cast<size_t>(rm_thr) * kBwdCheckpoints * 4);
+    float* gbuf = ck + remarch_words(R);
     unsigned long long* next_chunk =
         reinterpret_cast<unsigned long long*>(gbuf + static_cast<size_t>(sc.n) * gs);
     // zero the accumulator and the claim counter behind it
@@ -545,15 +583,18 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
             persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, false>, kBwdBlock));
         k_backward<K, FM, FU, SH, false><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin,
                                                                      gbuf, gs, ovf, ovf_slots,
-                                                                     reinterpret_cast<float4*>(ck), next_chunk, order);
+                                                                     reinterpret_cast<float4*>(ck), plist, next_chunk,
+                                                                     order);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     // rays without a complete stored list (all of them without stored lists)
-    const unsigned grid = persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, true>, kBwdBlock));
+    // (at most rm_thr lanes: the checkpoints and private lists are sized for them)
+    const unsigned grid =
+        persistent_grid(rm_thr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, true>, kBwdBlock));
     k_backward<K, FM, FU, SH, true><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf,
                                                                 gs, ovf, ovf_slots, reinterpret_cast<float4*>(ck),
-                                                                next_chunk + 1, nullptr);
+                                                                plist, next_chunk + 1, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t work = static_cast<int64_t>(sc.n) * (10 + P.F);

@@ -121,9 +121,10 @@ def coaxial_splats(n, opacity, seed):
 
 
 def test_many_rounds_past_the_checkpoints():
-    """k = 1 on 60 coaxial splats: 42 rounds, more than the 8 stored round
-    checkpoints, re-marched (stored capacity 4); the same rays traced again
-    by the backward (no stored lists) and in store mode at k = 16."""
+    """k = 1 on 60 coaxial splats: 42 rounds, more than the 16 round
+    checkpoints, re-marched (stored capacity 4: the re-march's private list
+    holds them); the same rays traced again by the backward (no stored
+    lists) and in store mode at k = 16."""
     surf, ro, rd, gO, gF, gD = coaxial_splats(60, 0.2, 30)
     note("deep rays k=1 re-march")
     _, a = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=4, recompute=False, k=1)
@@ -152,6 +153,22 @@ def test_retrace_longer_than_its_list_capacity():
     _, b = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=512, recompute=False, k=16)
     for name, _ in NAMES:
         np.testing.assert_allclose(r[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
+
+
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_remarch_longer_than_its_private_list(k):
+    """700 faint coaxial splats, every one composited, with 4 stored hits
+    per ray: the re-march holds only 512 hits in its private list, so these
+    rays are walked back round by round from checkpoints -- at k = 1 the
+    checkpoints are thinned five times (700 rounds, 16 checkpoints) -- and
+    the gradients must still match the FP64 oracle."""
+    surf, ro, rd, gO, gF, gD = coaxial_splats(700, 0.01, 34)
+    note(f"700-hit rays re-march k={k}")
+    fwd, a = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=4, recompute=False, k=k)
+    full, _ = gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=1024, recompute=False, k=16)
+    assert np.all(full["n_hits"] > 512) and np.array_equal(full["n_hits"], fwd["n_hits"])
+    ref = ograd.grad_given_hits(surf, ro, rd, lists_of(full), gO, gF, gD)
+    grad_close(a, ref)
 
 
 def test_finite_differences_on_surface_patch():
