@@ -62,8 +62,13 @@ def sh_basis_scipy(rd, deg: int) -> np.ndarray:
     return Y
 
 
-def composite_given_hits(mu, quat, scale, opac, feat, ro, rd, lists, sh_deg: int = -1):
-    """O, F, D, T of each ray from its ordered list (R, H) (-1 = padding)."""
+def composite_given_hits(mu, quat, scale, opac, feat, ro, rd, lists, sh_deg: int = -1, with_normal: bool = False):
+    """O, F, D, T of each ray from its ordered list (R, H) (-1 = padding).
+    With ``with_normal`` (the relighting blend of albedo, roughness and
+    normal with the same weights T alpha) F gains 3 channels: each hit's unit
+    normal turned to face the ray, -n where n . d > 0; the turn is a
+    piecewise-constant choice (no gradient), the normal itself carries the
+    gradient to the raw quaternion."""
     valid = lists >= 0
     idx = lists.clamp(min=0)
     m = mu[idx]                                  # (R, H, 3)
@@ -92,20 +97,26 @@ def composite_given_hits(mu, quat, scale, opac, feat, ro, rd, lists, sh_deg: int
         Y = torch.tensor(sh_basis_scipy(rd.detach().numpy(), sh_deg))          # (R, nb), no gradient
         k = f.reshape(f.shape[0], f.shape[1], nb, 3)
         f = torch.relu((Y[:, None, :, None] * k).sum(2) + 0.5)                 # view-dependent colour
+    if with_normal:
+        sgn = torch.where((n * d_r).sum(-1) > 0, -1.0, 1.0).detach()
+        f = torch.cat([f, sgn[..., None] * n], -1)
     F = (w[..., None] * f).sum(1)
     D = (w * tau).sum(1)
     Tend = T[:, -1] * (1.0 - alpha[:, -1]) if alpha.shape[1] else torch.ones_like(O)
     return O, F, D, Tend
 
 
-def grad_given_hits(surfels, ro, rd, lists, gO, gF, gD, sh_deg: int = -1):
-    """Gradients (dict of float64 numpy arrays) of L over given hit lists."""
+def grad_given_hits(surfels, ro, rd, lists, gO, gF, gD, sh_deg: int = -1, with_normal: bool = False):
+    """Gradients (dict of float64 numpy arrays) of L over given hit lists
+    (with ``with_normal``, gF holds F + 3 channels: the features, then the
+    facing normal)."""
     ts = [torch.tensor(np.asarray(a, dtype=np.float64), requires_grad=True) for a in surfels]
     feat = ts[4].reshape(ts[0].shape[0], -1)
     ro_t = torch.tensor(np.asarray(ro, dtype=np.float64)).reshape(-1, 3)
     rd_t = torch.tensor(np.asarray(rd, dtype=np.float64)).reshape(-1, 3)
     L_t = torch.tensor(np.asarray(lists, dtype=np.int64))
-    O, F, D, _ = composite_given_hits(ts[0], ts[1], ts[2], ts[3].reshape(-1), feat, ro_t, rd_t, L_t, sh_deg)
+    O, F, D, _ = composite_given_hits(ts[0], ts[1], ts[2], ts[3].reshape(-1), feat, ro_t, rd_t, L_t, sh_deg,
+                                      with_normal)
     gO_t = torch.tensor(np.asarray(gO, dtype=np.float64)).reshape(-1)
     gF_t = torch.tensor(np.asarray(gF, dtype=np.float64)).reshape(O.shape[0], -1)
     gD_t = torch.tensor(np.asarray(gD, dtype=np.float64)).reshape(-1)

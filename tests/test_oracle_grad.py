@@ -114,3 +114,64 @@ def test_autograd_matches_finite_differences(oracle_lib):
         err = np.abs(A[name][m] - Fd[name][m])
         assert np.all(err <= 1e-5 * (np.abs(A[name][m]) + scale)), (name, err.max(), scale)
     assert skipped < 0.05 * total
+
+
+def test_facing_normal_gradient_closed_form(oracle_lib):
+    """Lone splat, ray through its centre, upstream gradient only on the 3
+    normal channels: L = g_N . (o s n(q)) with s = -1 where n . d > 0
+    (the normal turned to face the ray), alpha = o independent of q at the
+    centre.  So dL/dq = o s J(q)^T g_N, J the Jacobian of the third column of
+    scipy's rotation matrix of the raw quaternion (central differences of
+    scipy, an implementation independent of the oracle's frame), dL/do =
+    s g_N . n, dL/dmu = 0 and the feature gradient is 0."""
+    from scipy.spatial.transform import Rotation
+    g = np.random.default_rng(13)
+
+    def ncol(q):  # scipy takes (x, y, z, w)
+        return Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()[:, 2]
+
+    for trial in range(12):
+        q = g.standard_normal(4)
+        mu = g.uniform(-1, 1, 3)
+        o = g.uniform(0.1, 1)
+        S = one(mu, q, g.uniform(0.01, 0.1, 2), o, g.uniform(0, 1, 2))
+        n = ncol(q)
+        d = g.standard_normal(3)
+        d /= np.linalg.norm(d)
+        if abs(np.dot(n, d)) < 0.2:
+            continue
+        sgn = -1.0 if np.dot(n, d) > 0 else 1.0
+        gN = g.standard_normal(3)
+        ro = mu - 1.5 * d
+        A = ograd.grad_given_hits(S, ro[None], d[None], np.array([[0]]), [0.0], [np.r_[0.0, 0.0, gN]], [0.0],
+                                  with_normal=True)
+        J = np.zeros((3, 4))
+        for k in range(4):
+            h = 1e-6
+            e = np.zeros(4)
+            e[k] = h
+            J[:, k] = (ncol(q + e) - ncol(q - e)) / (2 * h)
+        np.testing.assert_allclose(A["quat"][0], o * sgn * (J.T @ gN), rtol=1e-6, atol=1e-8)
+        assert abs(A["opac"][0] - sgn * np.dot(gN, n)) < 1e-10
+        np.testing.assert_allclose(A["mu"], 0, atol=1e-9)
+        np.testing.assert_allclose(A["feat"], 0, atol=1e-12)
+
+
+def test_facing_normal_autograd_matches_finite_differences(oracle_lib):
+    """With the facing-normal channels (the relighting blend), FP64 central
+    differences through the brute-force C oracle's own normal channels agree
+    with autograd over the oracle's hit lists."""
+    S, ro, rd, gO, gF, gD = _small_scene(14)
+    gF6 = np.random.default_rng(15).standard_normal((ro.shape[0], S[4].shape[1] + 3))
+    ref = oracle.trace(S, ro, rd, hit_cap=64, with_normal=True)
+    assert ref["F"].shape[1] == S[4].shape[1] + 3
+    A = ograd.grad_given_hits(S, ro, rd, ref["hits"], gO, gF6, gD, with_normal=True)
+    Fd, skipped = ograd.fd_grad(S, ro, rd, gO, gF6, gD, hit_cap=64, with_normal=True)
+    total = 0
+    for name in ("mu", "quat", "scale", "opac", "feat"):
+        m = ~np.isnan(Fd[name])
+        total += m.sum()
+        scale = np.abs(A[name]).mean() + 1e-12
+        err = np.abs(A[name][m] - Fd[name][m])
+        assert np.all(err <= 1e-5 * (np.abs(A[name][m]) + scale)), (name, err.max(), scale)
+    assert skipped < 0.05 * total
