@@ -99,12 +99,14 @@ typedef struct {
  * normalised ray direction.  out->feat and grad_in->g_feat are then R x 3;
  * grads->feat stays N x F.  k must be 16, 32 or 64; not for irgs_trace_packed. */
 #define IRGS_FLAG_SH 4u
-/* trace only (relighting: the trace alpha-blends albedo, roughness and the
- * normal): after the F <= 5 features, 3 more composited channels hold each
- * hit's unit normal, negated where it points along the ray (n . r_d > 0) so
- * that it faces the ray; out->feat is R x (F + 3).  Exclusive with
- * IRGS_FLAG_SH; k must be 16, 32 or 64; not for the backward or the packed
- * launch. */
+/* trace and backward (relighting details: the trace alpha-blends albedo,
+ * roughness and the normal with the same weights, Eq. 18): after the
+ * F <= 5 features, 3 more composited channels hold each hit's unit normal,
+ * negated where it points along the ray (n . r_d > 0) so that it faces the
+ * ray; out->feat and grad_in->g_feat are R x (F + 3), and the backward
+ * carries the normal channels' gradient through n to the raw quaternion
+ * (the turn itself is piecewise constant).  Exclusive with IRGS_FLAG_SH;
+ * k must be 16, 32 or 64; not for the packed launch. */
 #define IRGS_FLAG_NORMAL 8u
 /* scene build only: the binary tree under the 4-wide BVH is Karras' radix
  * tree over the sorted Morton codes (leaves stay in Morton order) instead

@@ -587,7 +587,6 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
 {
     irgs_status st = check_trace_common(s, p, R, ro, rd);
     if (st != IRGS_OK) return st;
-    if (p->flags & IRGS_FLAG_NORMAL) return fail(IRGS_E_INVALID, "IRGS_FLAG_NORMAL is forward-only (relighting)");
     if (!saved || !gin || !grads) return fail(IRGS_E_INVALID, "saved, grad_in and grads are required");
     if (R > 0 && !saved->n_hits) return fail(IRGS_E_INVALID, "saved->n_hits is required");
     if (R == 0 || s->n == 0) return IRGS_OK;
@@ -614,7 +613,7 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
     // walk (the retrace composites exactly as the forward did, so its lists
     // and T are the forward's); rays with more than kRetraceCap hits
     // re-march.  The accumulated gradients add into `grads` per batch.
-    const int fo = tp.sh_deg >= 0 ? 3 : s->F;  // composited (and upstream) channels
+    const int fo = tp.sh_deg >= 0 ? 3 : (tp.normals ? s->F + 3 : s->F);  // composited (and upstream) channels
     const size_t per_ray = static_cast<size_t>(kRetraceCap) * 8 + (3 + fo) * sizeof(float);
     const int64_t bmax = std::max<int64_t>(1, static_cast<int64_t>(kRetraceBytes / per_ray));
     const int64_t nbatch = (R + bmax - 1) / bmax;

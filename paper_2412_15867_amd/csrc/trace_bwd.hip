@@ -132,7 +132,12 @@ struct GradAcc {
 // With SH the features are RGB coefficients: the hit's colour is recomputed
 // exactly as in the forward (FP32), and the coefficient gradients are
 // T alpha g_F,c Y_j(d) wherever the channel is not clamped.
-template <int FM, int FU, bool SH>
+// With NRM (the relighting blend) the upstream holds F feature channels and
+// then 3 for the hit's normal turned to face the ray, s n with s = -1 where
+// n . d > 0; the turn is decided exactly as in the forward (the FP32 frame
+// of the record, the same dot product), and s T alpha g_N adds to the
+// gradient of n, which the rotation chain below carries to the quaternion.
+template <int FM, int FU, bool SH, bool NRM = false>
 __device__ __forceinline__ void grad_hit(const RawSurfels& raw, const TraceParams& P, int id, const Ray& ray,
                                          float Ti_f, float& S_f, float gO, const float* gF, float gD,
                                          HitGrad<FM>& h)
@@ -191,7 +196,20 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, const TraceParam
             c += double(gF[k]) * fv;
         }
 #pragma unroll
-        for (int k = 0; k < FM; ++k) h.g[10 + k] = static_cast<float>(wgt * gF[k]);
+        for (int k = 0; k < FM; ++k) h.g[10 + k] = (!NRM || k < F) ? static_cast<float>(wgt * gF[k]) : 0.0f;
+    }
+    double sN = 0.0, gN0 = 0.0, gN1 = 0.0, gN2 = 0.0;  // normal channels: turn and upstream
+    if constexpr (NRM) {
+        float tf[3], vf[3], nf[3];
+        quat_frame(qf, tf, vf, nf);
+        sN = dot3(nf[0], nf[1], nf[2], ray.dx, ray.dy, ray.dz) > 0.0f ? -1.0 : 1.0;
+#pragma unroll
+        for (int k = 0; k < FM; ++k) {
+            gN0 += k == F ? double(gF[k]) : 0.0;
+            gN1 += k == F + 1 ? double(gF[k]) : 0.0;
+            gN2 += k == F + 2 ? double(gF[k]) : 0.0;
+        }
+        c += sN * (gN0 * n0 + gN1 * n1 + gN2 * n2);
     }
     const double dA = Ti * (c - S);
     S_f = static_cast<float>(alpha * c + (1.0 - alpha) * S);
@@ -210,8 +228,10 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, const TraceParam
     h.g[0] = static_cast<float>(gt_den * n0 - gpx);
     h.g[1] = static_cast<float>(gt_den * n1 - gpy);
     h.g[2] = static_cast<float>(gt_den * n2 - gpz);
-    // dtau/dn = -(p - mu) / den;  du/dt_u = (p - mu) / s_u
-    const double gn0 = -gt_den * px, gn1 = -gt_den * py, gn2 = -gt_den * pz;
+    // dtau/dn = -(p - mu) / den;  du/dt_u = (p - mu) / s_u; the normal
+    // channels add s T alpha g_N
+    const double wn = wgt * sN;
+    const double gn0 = -gt_den * px + wn * gN0, gn1 = -gt_den * py + wn * gN1, gn2 = -gt_den * pz + wn * gN2;
     const double gu0 = au * px, gu1 = au * py, gu2 = au * pz;
     const double gv0 = av * px, gv1 = av * py, gv2 = av * pz;
     // derivatives of the rotation columns with respect to (w, x, y, z)
@@ -284,7 +304,7 @@ __device__ __forceinline__ LaneUp<FU> load_upstream(const GradIn& gin, int64_t r
 // are taken every other one is dropped and the stride doubles, so pass 2
 // re-collects at most stride - 1 extra rounds per round (instead of
 // re-marching from the last checkpoint for every round past them).
-template <int K, int FM, int FU, bool SH>
+template <int K, int FM, int FU, bool SH, bool NRM>
 __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
                                             const Ray& ray, const LaneUp<FU>& up, const GradAcc& acc, Stack& st,
                                             float4* ck, int64_t ck_stride, int* pid, float* pT)
@@ -338,7 +358,7 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
         for (int h = total - 1; h >= 0; --h) {
             const int id = pid[h];
             HitGrad<FM> hg;
-            grad_hit<FM, FU, SH>(raw, P, id, ray, pT[h], S, up.gO, up.gF, up.gD, hg);
+            grad_hit<FM, FU, SH, NRM>(raw, P, id, ray, pT[h], S, up.gO, up.gF, up.gD, hg);
             acc.direct<FM>(id, hg);
         }
         return;
@@ -373,7 +393,7 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
             entry<K>(kb, Tj, j, &pos, &Ti);
             const int id = __float_as_int(sc.rec[pos].c.w);
             HitGrad<FM> h;
-            grad_hit<FM, FU, SH>(raw, P, id, ray, Ti, S, up.gO, up.gF, up.gD, h);
+            grad_hit<FM, FU, SH, NRM>(raw, P, id, ray, Ti, S, up.gO, up.gF, up.gD, h);
             acc.direct<FM>(id, h);
         }
     }
@@ -388,7 +408,7 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
 // of 3 waves per SIMD (no spills for F <= 16), and the LDS table is sized so
 // that LDS allows as many (measured at 1M surfels, F = 8: 256 slots and 2
 // waves 33.3 ms; 64 slots and 3 waves 24.5 ms; no table 28.0 ms).
-template <int K, int FM, int FU, bool SH, bool RM>
+template <int K, int FM, int FU, bool SH, bool NRM, bool RM>
 __global__ __launch_bounds__(kBwdBlock) __attribute__((amdgpu_waves_per_eu(!RM && FM <= 16 ? 3 : 1)))
 void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                         const float* __restrict__ ro, const float* __restrict__ rd,
@@ -441,13 +461,13 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
             const bool complete = use_saved && nh_saved > 0 && nh_saved <= saved.H_cap;
             if (RM ? (!complete && nh_saved != 0) : complete) {
                 ray = load_ray(ro, rd, r);
-                up = load_upstream<FU>(gin, r, SH ? 3 : P.F);
+                up = load_upstream<FU>(gin, r, SH ? 3 : (NRM ? P.F + 3 : P.F));
                 if (up.any && sc.n > 0 && ray_valid(ray)) {
                     if constexpr (!RM) {
                         stored = true;
                         nh = nh_saved;
                     } else {
-                        bwd_remarch<K, FM, FU, SH>(sc, raw, P, ray, up, acc, st, myck, nthr, my_ids, my_T);
+                        bwd_remarch<K, FM, FU, SH, NRM>(sc, raw, P, ray, up, acc, st, myck, nthr, my_ids, my_T);
                     }
                 }
             }
@@ -467,7 +487,7 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
             int id = -1;
             if (valid) {
                 id = ids[h];
-                grad_hit<FM, FU, SH>(raw, P, id, ray, Ts[h], S, up.gO, up.gF, up.gD, hg);
+                grad_hit<FM, FU, SH, NRM>(raw, P, id, ray, Ts[h], S, up.gO, up.gF, up.gD, hg);
                 if (h < kNearHits) acc.table<FM>(id, hg);
             } else {
 #pragma unroll
@@ -541,7 +561,7 @@ __global__ void k_grad_out(int64_t n, int F, int gs, const float* __restrict__ g
     }
 }
 
-template <int K, int FM, int FU, bool SH>
+template <int K, int FM, int FU, bool SH, bool NRM = false>
 hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int64_t R, const float* ro,
                      const float* rd, const OutPtrs& saved, bool use_saved, const GradIn& gin, const GradOut& go,
                      int* ovf, int ovf_slots, float* ck, hipStream_t st)
@@ -580,8 +600,8 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
     }
     if (use_saved) {
         const unsigned grid =
-            persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, false>, kBwdBlock));
-        k_backward<K, FM, FU, SH, false><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin,
+            persistent_grid(nthr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, NRM, false>, kBwdBlock));
+        k_backward<K, FM, FU, SH, NRM, false><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin,
                                                                      gbuf, gs, ovf, ovf_slots,
                                                                      reinterpret_cast<float4*>(ck), plist, next_chunk,
                                                                      order);
@@ -591,8 +611,8 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
     // rays without a complete stored list (all of them without stored lists)
     // (at most rm_thr lanes: the checkpoints and private lists are sized for them)
     const unsigned grid =
-        persistent_grid(rm_thr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, true>, kBwdBlock));
-    k_backward<K, FM, FU, SH, true><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf,
+        persistent_grid(rm_thr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, NRM, true>, kBwdBlock));
+    k_backward<K, FM, FU, SH, NRM, true><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf,
                                                                 gs, ovf, ovf_slots, reinterpret_cast<float4*>(ck),
                                                                 plist, next_chunk + 1, nullptr);
     e = hipGetLastError();
@@ -611,8 +631,12 @@ hipError_t launch_k(const SceneView& sc, const RawSurfels& raw, const TraceParam
     if constexpr (K == 16 || K == 32 || K == 64) {  // SH: 48 coefficient gradients, 3 upstream channels
         if (P.sh_deg >= 0)
             return launch_kf<K, 48, 4, true>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
+        // relighting blend: F <= 5 features and 3 normal channels upstream
+        if (P.normals && P.F <= 5)
+            return launch_kf<K, 8, 8, false, true>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots,
+                                                   ck, st);
     }
-    if (P.sh_deg >= 0) return hipErrorInvalidValue;
+    if (P.sh_deg >= 0 || P.normals) return hipErrorInvalidValue;
     if (P.F <= 4)
         return launch_kf<K, 4, 4, false>(sc, raw, P, R, ro, rd, saved, use_saved, gin, go, ovf, ovf_slots, ck, st);
     if (P.F <= 8)

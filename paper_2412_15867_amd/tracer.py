@@ -73,7 +73,7 @@ class TraceConfig:
     # Monte Carlo workload: at 64 its backward takes 696 ms instead of 24.5)
     hit_cap: int = 256
     sh: bool = False             # features are RGB SH coefficients (view-dependent colour, 3 channels)
-    normals: bool = False        # forward only: 3 more channels, the ray-facing normal (relighting)
+    normals: bool = False        # 3 more channels, the ray-facing normal (relighting blend; differentiable)
     sort_rays: bool = False      # trace rays in the Morton order of their origins (same results)
 
     def flags(self) -> int:

@@ -104,6 +104,72 @@ def test_normal_channels_match_oracle_and_brute_force():
     validate(surf.astuple(), ro, rd, g, with_normal=True)
 
 
+@pytest.mark.parametrize("mode", ["store", "recompute", "remarch"])
+def test_normal_channels_backward_matches_oracle(mode):
+    """The relighting blend is differentiable (Eq. 18: albedo, roughness and
+    the normal blended with the trace's weights): upstream gradients on the
+    4 features and the 3 facing-normal channels, against the FP64 gradient
+    oracle over the same (validated) hit lists -- stored lists, lists traced
+    again by the backward, and rays re-marched past 4 stored hits."""
+    from oracle import grad as ograd
+    from paper_2412_15867_amd import TraceConfig, trace, trace_backward
+    surf = material_cube()
+    ro, rd = synth.pinhole_rays(32, 32)
+    R = ro.shape[0]
+    g = np.random.default_rng(96)
+    gO, gF, gD = (g.standard_normal(R).astype(F32), g.standard_normal((R, 7)).astype(F32),
+                  g.standard_normal(R).astype(F32))
+    note(f"normal-channel backward {mode}")
+    scene = make_scene(surf)
+    cfg = TraceConfig(k=16, normals=True, recompute=mode == "recompute")
+    res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=4 if mode == "remarch" else 256)
+    grads = trace_backward(scene, dev(ro), dev(rd), res, dev(gO), dev(gF), dev(gD), cfg=cfg)
+    full = to_np(trace(scene, dev(ro), dev(rd), TraceConfig(k=16, normals=True), hit_cap=256))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in grads.items()}
+    scene.close()
+    if mode == "remarch":
+        assert np.mean(full["n_hits"] > 4) > 0.2
+    validate(surf.astuple(), ro, rd, full, with_normal=True)
+    H = full["hit_ids"].shape[1]
+    lists = np.where(np.arange(H)[None, :] < full["n_hits"][:, None], full["hit_ids"], -1)
+    ref = ograd.grad_given_hits(surf.astuple(), ro, rd, lists, gO, gF, gD, with_normal=True)
+    worst = {}
+    for name, key in (("mu", "mu"), ("quat", "quat"), ("scale", "scale"), ("opacity", "opac"), ("feat", "feat")):
+        a = got[name].reshape(ref[key].shape)
+        b = ref[key]
+        err = np.abs(a - b) / (np.abs(b) + np.abs(b).mean() + 1e-30)
+        worst[name] = float(err.max())
+        assert err.max() <= 1e-3, (name, err.max())
+    note(f"  worst rel err {worst}")
+
+
+def test_normal_channels_autograd():
+    """TraceFn with the normal channels: its gradients equal the direct
+    backward's (the same kernels), and the quaternion gets a gradient from
+    the normal channels alone."""
+    from paper_2412_15867_amd import Scene, TraceConfig, TraceFn, trace, trace_backward
+    surf = material_cube()
+    ro, rd = synth.pinhole_rays(16, 16)
+    params = [dev(x).requires_grad_(True) for x in surf.astuple()]
+    scene = Scene(*[p.detach() for p in params])
+    scene.set_params(*params)
+    cfg = TraceConfig(k=16, normals=True)
+    note("TraceFn normals")
+    O, Fo, D = TraceFn.apply(*params, dev(ro), dev(rd), scene, cfg)
+    assert Fo.shape == (ro.shape[0], 7)
+    gN = torch.zeros_like(Fo)
+    gN[:, 4:] = 1.0
+    (Fo * gN).sum().backward()
+    res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=64)
+    direct = trace_backward(scene, dev(ro), dev(rd), res, None, gN.contiguous(), None, cfg=cfg)
+    for p, name in zip(params, ("mu", "quat", "scale", "opacity", "feat")):
+        torch.testing.assert_close(p.grad, direct[name].reshape(p.shape), rtol=1e-4, atol=1e-6)
+    assert torch.count_nonzero(params[1].grad) > 0
+    assert torch.count_nonzero(params[4].grad) == 0   # no upstream on the features
+    scene.close()
+
+
 def test_relight_lind_matches_oracle():
     """Split-sum indirect radiance of each ray against the oracle's: the
     oracle pre-integrates the sky itself and shades the FP64 replay of the
@@ -236,7 +302,7 @@ def test_weighted_shade_matches_oracle():
 
 def test_relight_chain_and_errors():
     """relight() is its stages composed (bit for bit) in both sampling
-    modes; the normal channels are forward only."""
+    modes; argument errors."""
     from paper_2412_15867_amd import (TraceConfig, _lib, brdf_table, env_cdf, env_prefilter, env_rays, mc_rays,
                                       relight, relight_lind, shade, trace, trace_backward)
     surf = material_cube()
@@ -270,8 +336,8 @@ def test_relight_chain_and_errors():
         relight(scene, x, n, wo, albedo, rough, env, u2, 3, Sp, sampling="stratified")
     ro, rd = synth.pinhole_rays(8, 8)
     res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=16)
-    with pytest.raises(_lib.IrgsError):       # forward only
-        trace_backward(scene, dev(ro), dev(rd), res, dev(np.ones(64, F32)), None, None,
+    with pytest.raises(ValueError):           # the normal channels' upstream has F + 3 columns
+        trace_backward(scene, dev(ro), dev(rd), res, None, dev(np.ones((64, 4), F32)), None,
                        cfg=TraceConfig(k=16, normals=True))
     with pytest.raises(_lib.IrgsError):       # SH and normals are exclusive (and 4 features are no SH set)
         trace(scene, dev(ro), dev(rd), TraceConfig(k=16, normals=True, sh=True))
