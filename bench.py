@@ -236,28 +236,31 @@ def run_c3(args):
     bwd_ms = np.array([e[2].elapsed_time(e[3]) for e in events])
     step_ms = wall * 1e3 / args.steps
 
-    # The same step with a 32-entry k-buffer: k only changes the number of
-    # rounds, never the result (same hits, same order), so this times the
-    # identical computation at the other buffer size.
+    # The same step at the other k-buffer size (the paper's 16, or 32 when
+    # the main run takes 16): k only changes the number of rounds, never the
+    # result (same hits, same order), so this times the identical
+    # computation at the other buffer size.
     alt = None
-    if args.k == 16 and not args.no_k32:
+    alt_k = 16 if args.k != 16 else 32
+    if not args.no_alt_k:
         cfg_main = cfg
-        cfg = TraceConfig(k=32, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh, sort_rays=args.sort_rays)
+        cfg = TraceConfig(k=alt_k, recompute=args.recompute, hit_cap=args.hit_cap, sh=sh, sort_rays=args.sort_rays)
         step(False)
         torch.cuda.synchronize()
-        ev32 = []
+        ev_alt = []
         t1 = time.perf_counter()
         for _ in range(args.steps):
-            ev32.append(step(True))
+            ev_alt.append(step(True))
         torch.cuda.synchronize()
-        ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
-        o32 = trace(scene, ro_d, rd_d, cfg, hit_cap=0)
-        o16 = trace(scene, ro_d, rd_d, cfg_main, hit_cap=0)
-        same = all(torch.equal(getattr(o16, k), getattr(o32, k)) for k in ("opacity", "feat", "depth", "T", "n_hits"))
-        alt = {"k": 32, "value": round(R / (ms32 * 1e-3) / 1e6, 3), "ms_per_step": round(ms32, 3),
-               "fwd_in_step_ms": round(float(np.median([e[1].elapsed_time(e[2]) for e in ev32])), 3),
-               "bwd_ms": round(float(np.median([e[2].elapsed_time(e[3]) for e in ev32])), 3),
-               "forward_output_bitwise_equal_to_k16": bool(same)}
+        ms_alt = (time.perf_counter() - t1) * 1e3 / args.steps
+        o_alt = trace(scene, ro_d, rd_d, cfg, hit_cap=0)
+        o_main = trace(scene, ro_d, rd_d, cfg_main, hit_cap=0)
+        same = all(torch.equal(getattr(o_main, k), getattr(o_alt, k))
+                   for k in ("opacity", "feat", "depth", "T", "n_hits"))
+        alt = {"k": alt_k, "value": round(R / (ms_alt * 1e-3) / 1e6, 3), "ms_per_step": round(ms_alt, 3),
+               "fwd_in_step_ms": round(float(np.median([e[1].elapsed_time(e[2]) for e in ev_alt])), 3),
+               "bwd_ms": round(float(np.median([e[2].elapsed_time(e[3]) for e in ev_alt])), 3),
+               f"forward_output_bitwise_equal_to_k{args.k}": bool(same)}
         cfg = cfg_main
 
     # hit statistics of this workload (the same forward, outputs kept)
@@ -305,7 +308,7 @@ def run_c3(args):
                                f"{', rays sorted by origin' if args.sort_rays else ''}",
                    "surfels": N, "rays": R, "features": F, "k": args.k, "tree": args.builder},
         "fwd_mrays_s": round(R / (fwd_only_ms * 1e-3) / 1e6, 3),
-        **({"k32": alt} if alt else {}),
+        **({f"k{alt_k}": alt} if alt else {}),
         "fwd_ms": round(fwd_only_ms, 3),
         "fwd_in_step_ms": round(f_med, 3),
         "bwd_ms": round(b_med, 3),
@@ -707,8 +710,9 @@ def main():
     ap.add_argument("--points", type=int, default=256 * 256)
     ap.add_argument("--dirs", type=int, default=64)
     ap.add_argument("--k", type=int, default=None,
-                    help="k-buffer size (default 16; c5: 64; serve: 32; pbr / relight: 64 up to 2^19 rays, else 32)")
-    ap.add_argument("--no-k32", action="store_true", help="default workload: skip the same step timed at k = 32")
+                    help="k-buffer size (default workload: 32; c5: 64; serve: 32; pbr / relight: 64 up to 2^19 rays, else 32; c1, c2: 16)")
+    ap.add_argument("--no-alt-k", action="store_true",
+                    help="default workload: skip the same step timed at the other k (16, or 32 when --k 16)")
     ap.add_argument("--leaf-size", type=int, default=0, help="surfels per leaf cluster (0: the library default)")
     ap.add_argument("--builder", default="ploc", choices=["ploc", "radix"],
                     help="binary tree under the 4-wide BVH: PLOC clustering or the Morton radix tree")
@@ -732,6 +736,8 @@ def main():
             args.k = 64  # 5M surfels: past the Infinity Cache every round's re-traversal costs HBM latency
         elif args.workload == "serve":
             args.k = 32  # scenes up to 3M surfels (packed launches take 16 or 32)
+        elif args.workload == "c3":
+            args.k = 32  # half the rounds of the paper's 16 at 3 waves per SIMD; bit-identical results
         else:
             args.k = 16  # the paper's k
     if args.sort_rays is None:
