@@ -431,7 +431,7 @@ size_t irgs_trace_bytes(int64_t R, int32_t F, uint32_t flags)
         const int64_t nb = (R + bmax - 1) / bmax;
         b += static_cast<size_t>((R + nb - 1) / nb) * per_ray + remarch_words(R) * sizeof(float);
     }
-    return b;  // plus, for a backward, 4 * ceil32(10 + F) bytes per surfel
+    return b;  // plus, for a backward, 4 * (ceil32(10 + F) + ceil32(12 + F)) bytes per surfel
 }
 
 irgs_status irgs_scene_create(int64_t n, int32_t F, const irgs_surfels* params, irgs_scene* out)
@@ -593,10 +593,16 @@ irgs_status irgs_trace_backward(irgs_scene s, const irgs_params* p, int64_t R, c
     const bool use_saved = !(p->flags & IRGS_FLAG_RECOMPUTE) && saved->hit_ids && saved->hit_T && saved->H_cap > 0;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const TraceParams tp = trace_params(p, s->F);
-    RawSurfels raw{s->p.mu, s->p.quat, s->p.scale, s->p.opacity, s->p.feat};
+    RawSurfels raw{s->p.mu, s->p.quat, s->p.scale, s->p.opacity, s->p.feat, nullptr, pack_stride(s->F)};
     GradIn g{gin->g_opacity, gin->g_feat, gin->g_depth};
     GradOut go{grads->mu, grads->quat, grads->scale, grads->opacity, grads->feat};
     const int slots = stack_need(s);  // the backward keeps its whole re-march stack in global memory
+    // the parameters packed one row per surfel, read by every hit's gradient
+    AsyncBuf pk;
+    hipError_t pe = pk.alloc(static_cast<size_t>(s->n) * raw.ps * sizeof(float), hs);
+    if (pe == hipSuccess) pe = pack_surfels(raw, s->n, s->F, static_cast<float*>(pk.p), hs);
+    if (pe != hipSuccess) return hip_fail(pe, "backward parameter pack");
+    raw.pk = static_cast<const float*>(pk.p);
     if (use_saved) {
         const size_t thr = static_cast<size_t>(trace_threads(R));
         AsyncBuf ovf, ck;

@@ -77,7 +77,17 @@ struct RawSurfels {
     const float* scale;
     const float* opac;
     const float* feat;
+    // The backward's copy of the same parameters, one row of `ps` floats per
+    // surfel id: (mu, o), q, (s_u, s_v, -, -), then the F features.  A hit
+    // then reads one 128-byte line (F <= 20) instead of five scattered ones.
+    const float* pk;
+    int ps;
 };
+
+// Floats per packed row: 12 + F rounded up to a multiple of 32.
+inline int pack_stride(int F) { return ((12 + F + 31) / 32) * 32; }
+// Fill pk (n rows of pack_stride(F) floats) from the raw arrays.
+hipError_t pack_surfels(const RawSurfels& raw, int64_t n, int F, float* pk, hipStream_t st);
 
 // Largest k-buffer / feature count the kernels are instantiated for.
 constexpr int kMaxK = 64;

@@ -144,11 +144,13 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, const TraceParam
 {
     const int F = P.F;
     const int64_t i = id;
-    const double mx = raw.mu[3 * i], my = raw.mu[3 * i + 1], mz = raw.mu[3 * i + 2];
-    const float4 qf = *reinterpret_cast<const float4*>(raw.quat + 4 * i);
-    const float2 sc = *reinterpret_cast<const float2*>(raw.scale + 2 * i);
+    const float* row = raw.pk + i * raw.ps;  // the packed copy of surfel i's parameters
+    const float4 mo = *reinterpret_cast<const float4*>(row);
+    const float4 qf = *reinterpret_cast<const float4*>(row + 4);
+    const float2 sc = *reinterpret_cast<const float2*>(row + 8);
+    const double mx = mo.x, my = mo.y, mz = mo.z;
     const double su = sc.x, sv = sc.y;
-    const double o = raw.opac[i];
+    const double o = mo.w;
     const double qn = sqrt(double(qf.x) * qf.x + double(qf.y) * qf.y + double(qf.z) * qf.z + double(qf.w) * qf.w);
     const double inv = 1.0 / qn;
     const double w = qf.x * inv, x = qf.y * inv, y = qf.z * inv, z = qf.w * inv;
@@ -168,7 +170,7 @@ __device__ __forceinline__ void grad_hit(const RawSurfels& raw, const TraceParam
     const double S = S_f;
 
     double c = gO + gD * tau;
-    const float* f = raw.feat + i * F;
+    const float* f = row + 12;
     const double wgt = Ti * alpha;
     if constexpr (SH) {
         float Y[16], col[3];
@@ -537,6 +539,23 @@ __global__ void k_ray_keys(int64_t R, const float* __restrict__ ro, const float*
     vals[r] = static_cast<uint32_t>(r);
 }
 
+// One packed row per surfel (see RawSurfels): consecutive threads take
+// consecutive surfels and write their rows whole.
+__global__ void k_pack(int64_t n, int F, int ps, const float* __restrict__ mu, const float* __restrict__ quat,
+                       const float* __restrict__ scale, const float* __restrict__ opac,
+                       const float* __restrict__ feat, float* __restrict__ pk)
+{
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    float4* row = reinterpret_cast<float4*>(pk + i * ps);
+    row[0] = make_float4(mu[3 * i], mu[3 * i + 1], mu[3 * i + 2], opac[i]);
+    row[1] = *reinterpret_cast<const float4*>(quat + 4 * i);
+    const float2 s = *reinterpret_cast<const float2*>(scale + 2 * i);
+    row[2] = make_float4(s.x, s.y, 0.0f, 0.0f);
+    float* f = pk + i * ps + 12;
+    for (int c = 0; c < F; ++c) f[c] = feat[i * F + c];
+}
+
 // gbuf (interleaved per surfel) added into the caller's gradient arrays.
 __global__ void k_grad_out(int64_t n, int F, int gs, const float* __restrict__ gbuf, GradOut go)
 {
@@ -651,6 +670,14 @@ hipError_t launch_k(const SceneView& sc, const RawSurfels& raw, const TraceParam
 }
 
 }  // namespace
+
+hipError_t pack_surfels(const RawSurfels& raw, int64_t n, int F, float* pk, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_pack<<<static_cast<unsigned>((n + 255) / 256), 256, 0, st>>>(n, F, pack_stride(F), raw.mu, raw.quat, raw.scale,
+                                                                   raw.opac, raw.feat, pk);
+    return hipGetLastError();
+}
 
 hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int k, int64_t R,
                            const float* ro, const float* rd, const OutPtrs& saved, bool use_saved,
