@@ -201,8 +201,9 @@ inline size_t backward_scratch_words(int64_t R, int64_t N, int F)
 {
     // the ray order is used only for gradients wider than the LDS table (the
     // backward sorts exactly when F > 8: keep the two conditions the same)
-    return remarch_words(R) + static_cast<size_t>(N) * grad_stride(F) + kBwdClaimWords +
-           (F > 8 ? ray_sort_words(R) : 0);
+    // (then the list of rays to re-march, R ints, and alignment slack)
+    return remarch_words(R) + static_cast<size_t>(N) * grad_stride(F) + kBwdClaimWords + static_cast<size_t>(R) +
+           128 + (F > 8 ? ray_sort_words(R) : 0);
 }
 hipError_t launch_backward(const SceneView& sc, const RawSurfels& raw, const TraceParams& P, int k, int64_t R,
                            const float* ro, const float* rd, const OutPtrs& saved, bool use_saved,

@@ -417,7 +417,8 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                         OutPtrs saved, bool use_saved, GradIn gin, float* gbuf,
                                                         int gs, int* ovf, int ovf_slots, float4* ck, int* plist,
                                                         unsigned long long* next_chunk,
-                                                        const uint32_t* __restrict__ order)
+                                                        const uint32_t* __restrict__ order, int* rm_list,
+                                                        unsigned long long* rm_count)
 {
     __shared__ int hkeys[kHashSlots];
     __shared__ float hvals[kLdsComp * kValRow];
@@ -441,26 +442,37 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
     float* my_T = RM ? reinterpret_cast<float*>(my_ids + kRemarchList) : nullptr;
     const GradAcc acc{hkeys, hvals, &hfilled, gbuf, gs, P.F};
     const int nc = 10 + P.F;
-    const int64_t chunks = (R + kBwdBlock - 1) / kBwdBlock;
+    // With stored lists the walk instance collects the rays it leaves (lists
+    // cut at H_cap) in rm_list; the re-march instance then claims chunks of
+    // that list only, instead of scanning every ray.
+    const bool listed = RM && use_saved && rm_list;
+    const int64_t Rw = listed ? static_cast<int64_t>(*rm_count) : R;
+    const int64_t chunks = (Rw + kBwdBlock - 1) / kBwdBlock;
     // chunks of kBwdBlock rays are claimed from a global counter as blocks
     // free up, so the launch drains evenly
     while (true) {
         if (tid == 0) claimed = static_cast<long long>(atomicAdd(next_chunk, 1ull));
-        acc.clear(tid);
+        // the re-march accumulates with direct atomics only: its instance
+        // neither clears nor flushes the table (most of its chunks hold no
+        // ray to re-march, and the table pass would be its whole cost)
+        if constexpr (!RM) acc.clear(tid);
         __syncthreads();
         const int64_t c = claimed;
         if (c >= chunks) break;
         // a chunk takes the next 64 rays of `order` or of the launch
         const int64_t slot = c * kBwdBlock + tid;
-        const int64_t r = slot < R && order ? static_cast<int64_t>(order[slot]) : slot;
+        const int64_t r = listed ? (slot < Rw ? static_cast<int64_t>(rm_list[slot]) : R)
+                                 : (slot < R && order ? static_cast<int64_t>(order[slot]) : slot);
         Ray ray{};
         LaneUp<FU> up{};
         int nh = 0;
         bool stored = false;
+        bool cut = false;  // walk instance: a ray left to the re-march
         if (r < R) {
             // each instance loads only the rays it owns
             const int nh_saved = saved.n_hits ? saved.n_hits[r] : -1;
             const bool complete = use_saved && nh_saved > 0 && nh_saved <= saved.H_cap;
+            cut = !RM && !complete && nh_saved != 0;
             if (RM ? (!complete && nh_saved != 0) : complete) {
                 ray = load_ray(ro, rd, r);
                 up = load_upstream<FU>(gin, r, SH ? 3 : (NRM ? P.F + 3 : P.F));
@@ -471,6 +483,19 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                     } else {
                         bwd_remarch<K, FM, FU, SH, NRM>(sc, raw, P, ray, up, acc, st, myck, nthr, my_ids, my_T);
                     }
+                }
+            }
+        }
+        if constexpr (!RM) {
+            if (rm_list) {  // one atomic per wave for the rays it leaves
+                const uint64_t m = __ballot(cut);
+                if (m) {
+                    const int rank = __popcll(m & __lanemask_lt());
+                    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+                    unsigned long long base = 0;
+                    if (cut && rank == 0) base = atomicAdd(rm_count, static_cast<unsigned long long>(__popcll(m)));
+                    base = __shfl(base, leader);
+                    if (cut) rm_list[base + rank] = static_cast<int>(r);
                 }
             }
         }
@@ -510,8 +535,10 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
             }
             __syncthreads();
         }
-        __syncthreads();
-        acc.flush(tid);
+        if constexpr (!RM) {
+            __syncthreads();
+            acc.flush(tid);
+        }
         __syncthreads();
     }
 }
@@ -592,6 +619,9 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
     float* gbuf = ck + remarch_words(R);
     unsigned long long* next_chunk =
         reinterpret_cast<unsigned long long*>(gbuf + static_cast<size_t>(sc.n) * gs);
+    unsigned long long* rm_count = next_chunk + 2;  // zeroed with the claim counters
+    char* after_claims = reinterpret_cast<char*>(next_chunk) + kBwdClaimWords * sizeof(float);
+    int* rm_list = reinterpret_cast<int*>((reinterpret_cast<uintptr_t>(after_claims) + 255) & ~static_cast<uintptr_t>(255));
     // zero the accumulator and the claim counter behind it
     hipError_t e = fill_u32(gbuf, static_cast<int64_t>(sc.n) * gs + kBwdClaimWords, 0u, st);
     if (e != hipSuccess) return e;
@@ -603,7 +633,7 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
     const uint32_t* order = nullptr;
     // (the condition on P.F is the one the scratch is sized by)
     if (P.F > kLdsFeat && use_saved && saved.O && saved.D && ray_sort_words(R) > 0 && sc.n > 0) {
-        char* p = reinterpret_cast<char*>(next_chunk) + kBwdClaimWords * sizeof(float);
+        char* p = reinterpret_cast<char*>(rm_list + R);
         p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~static_cast<uintptr_t>(255));
         uint64_t* k0 = reinterpret_cast<uint64_t*>(p);
         uint64_t* k1 = k0 + R;
@@ -623,7 +653,7 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
         k_backward<K, FM, FU, SH, NRM, false><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin,
                                                                      gbuf, gs, ovf, ovf_slots,
                                                                      reinterpret_cast<float4*>(ck), plist, next_chunk,
-                                                                     order);
+                                                                     order, rm_list, rm_count);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -633,7 +663,7 @@ hipError_t launch_kf(const SceneView& sc, const RawSurfels& raw, const TracePara
         persistent_grid(rm_thr / kBwdBlock, resident_blocks(k_backward<K, FM, FU, SH, NRM, true>, kBwdBlock));
     k_backward<K, FM, FU, SH, NRM, true><<<grid, kBwdBlock, 0, st>>>(sc, raw, P, R, ro, rd, saved, use_saved, gin, gbuf,
                                                                 gs, ovf, ovf_slots, reinterpret_cast<float4*>(ck),
-                                                                plist, next_chunk + 1, nullptr);
+                                                                plist, next_chunk + 1, nullptr, rm_list, rm_count);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t work = static_cast<int64_t>(sc.n) * (10 + P.F);
