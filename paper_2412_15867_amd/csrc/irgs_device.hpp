@@ -156,24 +156,30 @@ __device__ __forceinline__ SurfelRec load_rec(const SurfelRec* __restrict__ rec,
 }
 
 // Hit keys: (tau, leaf position) packed into one 64-bit integer whose
-// unsigned order is the lexicographic order (the float maps to an unsigned
-// integer of the same order: sign-flipped when negative).
+// unsigned order is the lexicographic order.  tau maps to a 32-bit unsigned
+// m of the same order (sign-flipped when negative); the key is the top bit,
+// then m, then the 31-bit position.  With the top bit set every key read as
+// a double is negative, finite and normal (m's high bits equal to all ones or
+// all zeros would need a NaN tau), so the FP64 order of keys is the reverse
+// of their integer order: the k-buffer merges with FP64 min and max.
 __device__ __forceinline__ uint64_t hit_key(float tau, int pos)
 {
     const uint32_t u = __float_as_uint(tau);
     const uint32_t m = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    return (static_cast<uint64_t>(m) << 32) | static_cast<uint32_t>(pos);
+    return 0x8000000000000000ull | (static_cast<uint64_t>(m) << 31) | static_cast<uint32_t>(pos);
 }
 
 __device__ __forceinline__ float key_tau(uint64_t k)
 {
-    const uint32_t m = static_cast<uint32_t>(k >> 32);
+    const uint32_t m = static_cast<uint32_t>(k >> 31);
     return __uint_as_float((m & 0x80000000u) ? (m & 0x7fffffffu) : ~m);
 }
 
-__device__ __forceinline__ int key_pos(uint64_t k) { return static_cast<int>(static_cast<uint32_t>(k)); }
+__device__ __forceinline__ int key_pos(uint64_t k) { return static_cast<int>(static_cast<uint32_t>(k) & 0x7fffffffu); }
 
-constexpr uint64_t kKeyNone = ~0ull;  // larger than every key
+// Above every key as an integer (a finite tau gives at most 0xFFBF...), and
+// -inf read as a double.  Key 0 (below every key) marks a ray's first round.
+constexpr uint64_t kKeyNone = 0xFFF0000000000000ull;
 
 // The root node's box: the union of its non-empty child slots (lo > hi
 // when the scene is empty).

@@ -41,22 +41,40 @@ struct KBuf {
 
     // Insert `key` when `ins` holds (then key is below the last entry; keys
     // are unique); the last entry falls off the end and is returned
-    // (kKeyNone when nothing fell off).  Branch-free: every comparison is
-    // against the new key, so they are independent; then, from the back, an
-    // entry takes its predecessor when the key sorts before the predecessor,
-    // else the key when it sorts before the entry.  With ins false nothing
-    // moves.
+    // (kKeyNone when nothing fell off).  Read as doubles the keys are in
+    // reverse order and kKeyNone is -inf, so entry j of the merged sequence
+    // is FP64 min(entry j-1, max(key, entry j)) of the old one: two
+    // full-rate instructions per entry, all independent (a 64-bit compare
+    // and four selects per entry as integers).  With ins false the key is
+    // kKeyNone and nothing moves (the entries are sorted).
     __device__ __forceinline__ uint64_t insert_if(bool ins, uint64_t key)
     {
-        bool lt[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) lt[j] = ins && key < k[j];
         const uint64_t out = ins ? k[K - 1] : kKeyNone;
+        const double x = as_f64(ins ? key : kKeyNone);
 #pragma unroll
-        for (int j = K - 1; j > 0; --j) k[j] = lt[j - 1] ? k[j - 1] : (lt[j] ? key : k[j]);  // lt[j-1] implies lt[j]
-        k[0] = lt[0] ? key : k[0];
+        for (int j = K - 1; j > 0; --j) k[j] = bits_of(f64_min(as_f64(k[j - 1]), f64_max(x, as_f64(k[j]))));
+        k[0] = bits_of(f64_max(x, as_f64(k[0])));
         cnt += (ins && cnt < K) ? 1 : 0;
         return out;
+    }
+
+  private:
+    static __device__ __forceinline__ double as_f64(uint64_t b) { return __longlong_as_double(static_cast<long long>(b)); }
+    static __device__ __forceinline__ uint64_t bits_of(double d) { return static_cast<uint64_t>(__double_as_longlong(d)); }
+    // The instructions themselves: through the fmin/fmax builtins the
+    // compiler first quiets every loop-carried entry (a third instruction per
+    // entry), which keys, never NaN, do not need.
+    static __device__ __forceinline__ double f64_min(double a, double b)
+    {
+        double r;
+        asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+        return r;
+    }
+    static __device__ __forceinline__ double f64_max(double a, double b)
+    {
+        double r;
+        asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+        return r;
     }
 };
 

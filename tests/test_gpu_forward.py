@@ -263,6 +263,29 @@ def test_tmin_tmax_window(c1):
     assert np.all(g["n_hits"][g["O"] == 0] == 0)
 
 
+@pytest.mark.parametrize("k", [2, 16, 32])
+def test_negative_t_min_mixed_sign_depths(c1, k):
+    """Origins moved into the cube and t_min = -10: most rays have hits
+    behind their origin (negative depth) and in front, so their keys change
+    sign within one buffer.  Oracle-validated; bitwise equal to brute force
+    and to k = 16."""
+    sc, ro, rd = c1
+    ro_in = (ro + 2.5 * rd).astype(np.float32)
+    note(f"negative t_min, k={k}")
+    g = run(sc, ro_in, rd, hit_cap=256, k=k, t_min=-10.0)
+    validate(sc.astuple(), ro_in, rd, g, t_min=-10.0)
+    b = run(sc, ro_in, rd, hit_cap=256, k=k, t_min=-10.0, brute_force=True)
+    ref = run(sc, ro_in, rd, hit_cap=256, k=16, t_min=-10.0)
+    for key in ("O", "F", "D", "T", "n_hits"):
+        assert np.array_equal(g[key], b[key]), key
+        assert np.array_equal(g[key], ref[key]), key
+    # most rays composite hits on both sides of their origin: they have hits
+    # in front (t_min = 0) and more with the window opened behind
+    front = run(sc, ro_in, rd, hit_cap=256, k=k, t_min=0.0)
+    both = (front["n_hits"] > 0) & (g["n_hits"] > front["n_hits"])
+    assert both.mean() > 0.5
+
+
 def test_paper_cutoff_003(c1):
     """The paper's transmittance cutoff 0.03."""
     sc, ro, rd = c1
