@@ -442,6 +442,11 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
     float* my_T = RM ? reinterpret_cast<float*>(my_ids + kRemarchList) : nullptr;
     const GradAcc acc{hkeys, hvals, &hfilled, gbuf, gs, P.F};
     const int nc = 10 + P.F;
+    // The scatter below hands lane l the elements l, l + 64, ... of a
+    // block's hits x components: its first (hit, component) pair and the step
+    // between pairs, so that no element needs an integer division.
+    const int sc_h0 = tid / nc, sc_c0 = tid - sc_h0 * nc;
+    const int sc_dh = kBwdBlock / nc, sc_dc = kBwdBlock - sc_dh * nc;
     // With stored lists the walk instance collects the rays it leaves (lists
     // cut at H_cap) in rm_list; the re-march instance then claims chunks of
     // that list only, instead of scanning every ray.
@@ -520,20 +525,33 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
 #pragma unroll
                 for (int k = 0; k < 10 + FM; ++k) hg.g[k] = 0.0f;
             }
-            stage_id[tid] = id;
+            // What the table did not take goes to global memory; a step whose
+            // hits the table took whole (a block is one wave: the branch is
+            // uniform) skips the staging.
+            bool left = false;
 #pragma unroll
-            for (int k = 0; k < 10 + FM; ++k) stage[k * kRow + tid] = hg.g[k];
-            __syncthreads();
-            // Transposed scatter: lane l takes component (q*64 + l) % nc of
-            // hit (q*64 + l) / nc, so consecutive lanes add consecutive
-            // components of one surfel -- a few cache lines per instruction.
-            for (int flat = tid; flat < kBwdBlock * nc; flat += kBwdBlock) {
-                const int hit = flat / nc, comp = flat - hit * nc;
-                const int sid = stage_id[hit];
-                const float v = stage[comp * kRow + hit];
-                if (sid >= 0 && v != 0.0f) atomicAdd(gbuf + static_cast<int64_t>(sid) * gs + comp, v);
+            for (int k = 0; k < 10 + FM; ++k) left = left || hg.g[k] != 0.0f;
+            if (__ballot(left)) {
+                stage_id[tid] = id;
+#pragma unroll
+                for (int k = 0; k < 10 + FM; ++k) stage[k * kRow + tid] = hg.g[k];
+                __syncthreads();
+                // Transposed scatter: lane l takes component (q*64 + l) % nc
+                // of hit (q*64 + l) / nc, so consecutive lanes add consecutive
+                // components of one surfel -- a few cache lines per instruction.
+                for (int hit = sc_h0, comp = sc_c0; hit < kBwdBlock;) {
+                    const int sid = stage_id[hit];
+                    const float v = stage[comp * kRow + hit];
+                    if (sid >= 0 && v != 0.0f) atomicAdd(gbuf + static_cast<int64_t>(sid) * gs + comp, v);
+                    hit += sc_dh;
+                    comp += sc_dc;
+                    if (comp >= nc) {
+                        comp -= nc;
+                        ++hit;
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
         if constexpr (!RM) {
             __syncthreads();
