@@ -531,15 +531,23 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
             bool left = false;
 #pragma unroll
             for (int k = 0; k < 10 + FM; ++k) left = left || hg.g[k] != 0.0f;
-            if (__ballot(left)) {
-                stage_id[tid] = id;
+            const uint64_t lm = __ballot(left);
+            if (lm) {
+                // only the hits with something left are staged, packed into
+                // the first rows
+                const int n_left = __popcll(lm);
+                if (left) {
+                    const int row = __popcll(lm & __lanemask_lt());
+                    stage_id[row] = id;
 #pragma unroll
-                for (int k = 0; k < 10 + FM; ++k) stage[k * kRow + tid] = hg.g[k];
+                    for (int k = 0; k < 10 + FM; ++k) stage[k * kRow + row] = hg.g[k];
+                }
                 __syncthreads();
                 // Transposed scatter: lane l takes component (q*64 + l) % nc
-                // of hit (q*64 + l) / nc, so consecutive lanes add consecutive
-                // components of one surfel -- a few cache lines per instruction.
-                for (int hit = sc_h0, comp = sc_c0; hit < kBwdBlock;) {
+                // of staged hit (q*64 + l) / nc, so consecutive lanes add
+                // consecutive components of one surfel -- a few cache lines per
+                // instruction.
+                for (int hit = sc_h0, comp = sc_c0; hit < n_left;) {
                     const int sid = stage_id[hit];
                     const float v = stage[comp * kRow + hit];
                     if (sid >= 0 && v != 0.0f) atomicAdd(gbuf + static_cast<int64_t>(sid) * gs + comp, v);
