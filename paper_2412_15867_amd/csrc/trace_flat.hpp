@@ -467,8 +467,15 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                         out.hit_ids[at] = id;
                         if (out.hit_T) out.hit_T[at] = T;
                     } else if (nh & 1) {  // the second of a pair: both in one 8-byte store each
-                        *reinterpret_cast<int2*>(out.hit_ids + at - 1) = make_int2(pend_id, id);
-                        if (out.hit_T) *reinterpret_cast<float2*>(out.hit_T + at - 1) = make_float2(pend_T, T);
+                        // streaming stores: the lists are read by the backward,
+                        // not by this launch, so they need no room in L2
+                        __builtin_nontemporal_store(
+                            (static_cast<long long>(static_cast<uint32_t>(id)) << 32) | static_cast<uint32_t>(pend_id),
+                            reinterpret_cast<long long*>(out.hit_ids + at - 1));
+                        if (out.hit_T)
+                            __builtin_nontemporal_store(
+                                (static_cast<long long>(__float_as_uint(T)) << 32) | __float_as_uint(pend_T),
+                                reinterpret_cast<long long*>(out.hit_T + at - 1));
                     } else {
                         pend_id = id;
                         pend_T = T;
