@@ -329,10 +329,11 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         if ((bn | bl | bo) == 0) break;
         const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
         // node steps count double against leaf steps: a node step hands its
-        // lanes new items, and a leaf step that waits loses nothing; with the
-        // normal channels (relighting) compositing and fetch steps count
-        // double too
-        constexpr int kOtherW = CM == kColNormal ? 2 : 1;
+        // lanes new items, and a leaf step that waits loses nothing;
+        // compositing and fetch steps count double against both, except with
+        // SH colour, whose compositing step (the basis and 48 coefficients)
+        // is the costliest step
+        constexpr int kOtherW = CM == kColSH ? 1 : 2;
         if (cn > 0 && 2 * cn >= cl && cn >= kOtherW * co) {
             if (want_node) {
                 if constexpr (CT) ++ct.nodes;
