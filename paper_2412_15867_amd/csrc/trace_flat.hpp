@@ -330,10 +330,12 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
         const int cn = __popcll(bn), cl = __popcll(bl), co = __popcll(bo);
         // node steps count double against leaf steps: a node step hands its
         // lanes new items, and a leaf step that waits loses nothing;
-        // compositing and fetch steps count double against both, except with
-        // SH colour, whose compositing step (the basis and 48 coefficients)
-        // is the costliest step
-        constexpr int kOtherW = CM == kColSH ? 1 : 2;
+        // compositing and fetch steps count double against both with the
+        // normal channels, and with plain features for K >= 32 (measured:
+        // at K = 16 on a 200K-surfel scene with 24 hits per ray the double
+        // weight costs 14%; the SH compositing step, with the basis and 48
+        // coefficients, is the costliest step and never takes it)
+        constexpr int kOtherW = (CM == kColNormal || (CM == kColPlain && K >= 32)) ? 2 : 1;
         if (cn > 0 && 2 * cn >= cl && cn >= kOtherW * co) {
             if (want_node) {
                 if constexpr (CT) ++ct.nodes;
