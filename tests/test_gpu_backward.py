@@ -31,10 +31,11 @@ def grad_close(g_gpu, g_ref, rel=1e-3):
     return worst
 
 
-def gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=256, recompute=False, k=16, T_min=1e-4, sort_rays=False):
+def gpu_fwd_bwd(surf, ro, rd, gO, gF, gD, hit_cap=256, recompute=False, k=16, T_min=1e-4, sort_rays=False,
+                t_min=0.0):
     from paper_2412_15867_amd import TraceConfig, trace, trace_backward
     scene = make_scene(surf)
-    cfg = TraceConfig(k=k, T_min=T_min, recompute=recompute, sort_rays=sort_rays)
+    cfg = TraceConfig(k=k, T_min=T_min, recompute=recompute, sort_rays=sort_rays, t_min=t_min)
     res = trace(scene, dev(ro), dev(rd), cfg, hit_cap=hit_cap)
     grads = trace_backward(scene, dev(ro), dev(rd), res, dev(gO), dev(gF), dev(gD), cfg=cfg)
     torch.cuda.synchronize()
@@ -103,6 +104,27 @@ def test_small_hit_cap_falls_back_to_recompute(cube):
     _, b = gpu_fwd_bwd(sc.astuple(), ro, rd, gO, gF, gD, hit_cap=256)
     for name, _ in NAMES:
         np.testing.assert_allclose(a[name], b[name], rtol=1e-4, atol=1e-6 * np.abs(b[name]).max())
+
+
+@pytest.mark.parametrize("k", [4, 32])
+def test_negative_t_min_store_and_remarch(cube, k):
+    """Origins inside the cube and t_min = -10: hits behind and in front of
+    the origin in one list.  Stored lists: the gradients match the FP64
+    oracle on the validated lists; a stored capacity of 4 (the rest
+    re-marched) and the recompute mode give the same gradients."""
+    sc, ro, rd, gO, gF, gD = cube
+    ro_in = (ro + 2.5 * rd).astype(np.float32)
+    note(f"cube backward, negative t_min, k={k}")
+    fwd, a = gpu_fwd_bwd(sc.astuple(), ro_in, rd, gO, gF, gD, k=k, t_min=-10.0)
+    validate(sc.astuple(), ro_in, rd, fwd, t_min=-10.0)
+    ref = ograd.grad_given_hits(sc.astuple(), ro_in, rd, lists_of(fwd), gO, gF, gD)
+    grad_close(a, ref)
+    fwd4, b = gpu_fwd_bwd(sc.astuple(), ro_in, rd, gO, gF, gD, k=k, t_min=-10.0, hit_cap=4)
+    assert np.mean(fwd4["n_hits"] > 4) > 0.2
+    _, c = gpu_fwd_bwd(sc.astuple(), ro_in, rd, gO, gF, gD, k=k, t_min=-10.0, hit_cap=0, recompute=True)
+    for name, _ in NAMES:
+        np.testing.assert_allclose(b[name], a[name], rtol=1e-4, atol=1e-6 * np.abs(a[name]).max())
+        np.testing.assert_allclose(c[name], a[name], rtol=1e-4, atol=1e-6 * np.abs(a[name]).max())
 
 
 def coaxial_splats(n, opacity, seed):
