@@ -26,14 +26,21 @@ namespace irgs {
 namespace {
 
 constexpr int kBwdBlock = 64;    // one wave per block: one table per 64 consecutive rays
-constexpr int kHashBits = 6;       // 64 slots: a small table leaves LDS for more resident waves
-constexpr int kHashSlots = 1 << kHashBits;
 constexpr int kHashProbes = 8;
-constexpr int kHashFill = kHashSlots * 3 / 4;  // no new keys once this many slots are taken
-constexpr int kNearHits = 24;    // only a ray's first hits (shared by neighbouring rays) use the table
 constexpr int kLdsFeat = 8;      // feature gradients pre-reduced in LDS (the rest go straight to global)
 constexpr int kLdsComp = 10 + kLdsFeat;
-constexpr int kValRow = kHashSlots + 1;  // value rows padded by a word: a row per component, lanes reading one slot hit different banks
+// The LDS table's slots and the hits of a ray that use it (only its first
+// hits, shared by neighbouring rays).  The table is sized so that LDS allows
+// the walk's 3 waves per SIMD: 96 slots with at most 8 features staged
+// (12.3 KB per one-wave block), 64 with more (at 1M surfels, F = 8: 64 slots
+// and 24 near hits 19.2 ms, 96 and 32 18.2 ms, 96 and 40 18.4 ms, 104 and
+// 32 18.7 ms).
+template <int FM>
+struct TableShape {
+    static constexpr int slots = FM <= 8 ? 96 : 64;
+    static constexpr int near_hits = FM <= 8 ? 32 : 24;
+    static constexpr int val_row = slots + 1;
+};
 
 // Per-surfel gradient components of one hit: mu (3), raw quaternion (4),
 // scales (2), opacity (1), features (F).
@@ -47,8 +54,11 @@ struct HitGrad {
 // (LDS float atomics) and written to global memory once per chunk of rays.
 // A surfel that finds no slot within kHashProbes probes goes straight to the
 // global atomics.
+template <int kSlots>
 struct GradAcc {
-    int* keys;     // kHashSlots, -1 = empty
+    static constexpr int kFill = kSlots * 3 / 4;  // no new keys once this many slots are taken
+    static constexpr int kValRow = kSlots + 1;    // value rows padded by a word: lanes reading one slot hit different banks
+    int* keys;     // kSlots, -1 = empty
     float* vals;   // [kLdsComp][kValRow]
     int* filled;   // slots taken in this chunk
     float* gbuf;   // per-surfel interleaved accumulator: gbuf[id * gs + c]
@@ -72,8 +82,8 @@ struct GradAcc {
     template <int FM>
     __device__ __forceinline__ bool table(int id, HitGrad<FM>& h) const
     {
-        uint32_t slot = (static_cast<uint32_t>(id) * 2654435761u) >> (32 - kHashBits);
-        const bool may_insert = *filled < kHashFill;
+        uint32_t slot = __umulhi(static_cast<uint32_t>(id) * 2654435761u, static_cast<uint32_t>(kSlots));
+        const bool may_insert = *filled < kFill;
         int found = -1;
         for (int p = 0; p < kHashProbes; ++p) {
             const int k = keys[slot];
@@ -90,7 +100,7 @@ struct GradAcc {
                     break;
                 }
             }
-            slot = (slot + 1) & (kHashSlots - 1);
+            slot = slot + 1 == kSlots ? 0 : slot + 1;
         }
         if (found < 0) return false;
 #pragma unroll
@@ -106,7 +116,7 @@ struct GradAcc {
     __device__ __forceinline__ void flush(int tid) const
     {
         const int nc = 10 + (F < kLdsFeat ? F : kLdsFeat);
-        for (int flat = tid; flat < kHashSlots * nc; flat += kBwdBlock) {
+        for (int flat = tid; flat < kSlots * nc; flat += kBwdBlock) {
             const int slot = flat / nc, c = flat - slot * nc;
             const int id = keys[slot];
             if (id < 0) continue;
@@ -118,7 +128,7 @@ struct GradAcc {
     __device__ __forceinline__ void clear(int tid) const
     {
         if (tid == 0) *filled = 0;
-        for (int i = tid; i < kHashSlots; i += kBwdBlock) keys[i] = -1;
+        for (int i = tid; i < kSlots; i += kBwdBlock) keys[i] = -1;
         for (int i = tid; i < kLdsComp * kValRow; i += kBwdBlock) vals[i] = 0.0f;
     }
 };
@@ -306,9 +316,9 @@ __device__ __forceinline__ LaneUp<FU> load_upstream(const GradIn& gin, int64_t r
 // are taken every other one is dropped and the stride doubles, so pass 2
 // re-collects at most stride - 1 extra rounds per round (instead of
 // re-marching from the last checkpoint for every round past them).
-template <int K, int FM, int FU, bool SH, bool NRM>
+template <int K, int FM, int FU, bool SH, bool NRM, class Acc>
 __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfels& raw, const TraceParams& P,
-                                            const Ray& ray, const LaneUp<FU>& up, const GradAcc& acc, Stack& st,
+                                            const Ray& ray, const LaneUp<FU>& up, const Acc& acc, Stack& st,
                                             float4* ck, int64_t ck_stride, int* pid, float* pT)
 {
     float S = 0.0f;
@@ -361,7 +371,7 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
             const int id = pid[h];
             HitGrad<FM> hg;
             grad_hit<FM, FU, SH, NRM>(raw, P, id, ray, pT[h], S, up.gO, up.gF, up.gD, hg);
-            acc.direct<FM>(id, hg);
+            acc.template direct<FM>(id, hg);
         }
         return;
     }
@@ -396,7 +406,7 @@ __device__ __forceinline__ void bwd_remarch(const SceneView& sc, const RawSurfel
             const int id = __float_as_int(sc.rec[pos].c.w);
             HitGrad<FM> h;
             grad_hit<FM, FU, SH, NRM>(raw, P, id, ray, Ti, S, up.gO, up.gF, up.gD, h);
-            acc.direct<FM>(id, h);
+            acc.template direct<FM>(id, h);
         }
     }
 }
@@ -420,8 +430,9 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
                                                         const uint32_t* __restrict__ order, int* rm_list,
                                                         unsigned long long* rm_count)
 {
-    __shared__ int hkeys[kHashSlots];
-    __shared__ float hvals[kLdsComp * kValRow];
+    using Shape = TableShape<FM>;
+    __shared__ int hkeys[Shape::slots];
+    __shared__ float hvals[kLdsComp * Shape::val_row];
     __shared__ int hfilled;
     __shared__ long long claimed;
     __shared__ int stage_id[kBwdBlock];
@@ -440,7 +451,7 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
     float4* myck = RM ? ck + gtid : nullptr;
     int* my_ids = RM ? plist + gtid * (2 * kRemarchList) : nullptr;
     float* my_T = RM ? reinterpret_cast<float*>(my_ids + kRemarchList) : nullptr;
-    const GradAcc acc{hkeys, hvals, &hfilled, gbuf, gs, P.F};
+    const GradAcc<Shape::slots> acc{hkeys, hvals, &hfilled, gbuf, gs, P.F};
     const int nc = 10 + P.F;
     // The scatter below hands lane l the elements l, l + 64, ... of a
     // block's hits x components: its first (hit, component) pair and the step
@@ -520,7 +531,7 @@ void k_backward(SceneView sc, RawSurfels raw, TraceParams P, int64_t R,
             if (valid) {
                 id = ids[h];
                 grad_hit<FM, FU, SH, NRM>(raw, P, id, ray, Ts[h], S, up.gO, up.gF, up.gD, hg);
-                if (h < kNearHits) acc.table<FM>(id, hg);
+                if (h < Shape::near_hits) acc.template table<FM>(id, hg);
             } else {
 #pragma unroll
                 for (int k = 0; k < 10 + FM; ++k) hg.g[k] = 0.0f;
