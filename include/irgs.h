@@ -8,8 +8,10 @@
  *   - at p = r_o + tau r_d, u = (p-mu).t_u / s_u, v = (p-mu).t_v / s_v and
  *     alpha = o exp(-(u^2+v^2)/2)                                   (Eq. 7);
  *   - hits are collected by k-buffer marching (the k nearest after the last
- *     composited hit, per round) in exact (tau, id) order and alpha-blended
- *     front to back (Eq. 2), stopping once the transmittance T < T_min;
+ *     composited hit, per round) in exact depth order (hits at equal tau in
+ *     the order of the surfels' leaf positions in the tree) and
+ *     alpha-blended front to back (Eq. 2), stopping once the transmittance
+ *     T < T_min;
  *   - the surfel frame (t_u, t_v, n) is the column set of the rotation of
  *     the unit quaternion q = (w, x, y, z) (Sec. 3.1: quaternion + scaling
  *     parameterisation; Sec. 3.2: two tangents and their cross product).
