@@ -131,12 +131,14 @@ __device__ __forceinline__ bool cluster_miss(const SurfelRec& s, const Ray& ray,
     return (ta < lo && tb < lo) || (ta > t_max && tb > t_max) || wide;
 }
 
-// Stored hit lists are written two entries at a time (one 8-byte store for
-// the ids, one for the transmittances) when rows start 8-byte aligned.
+// Stored hit lists are written four entries at a time (one 16-byte
+// streaming store for the ids, one for the transmittances: the lists are read
+// by the backward, not by this launch, so they need no room in L2) when rows
+// start 16-byte aligned.
 __device__ __forceinline__ bool pair_stores(const OutPtrs& out)
 {
     const uintptr_t a = reinterpret_cast<uintptr_t>(out.hit_ids) | reinterpret_cast<uintptr_t>(out.hit_T);
-    return (out.H_cap & 1) == 0 && (a & 7) == 0;
+    return (out.H_cap & 3) == 0 && (a & 15) == 0;
 }
 
 template <int FM, int CM, bool CT, class Source>
@@ -282,8 +284,8 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
     int nh = 0;
     uint64_t after = 0;          // resume key; while compositing, the key just composited
     uint64_t pend = kKeyNone;    // hit key entering the buffer at the next iteration (mode kIns)
-    int pend_id = 0;             // stored hit list: an even entry waiting for its pair
-    float pend_T = 0.0f;
+    int pend_id = 0, pend_id1 = 0, pend_id2 = 0;  // stored hit list: entries waiting for their quad
+    float pend_T = 0.0f, pend_T1 = 0.0f, pend_T2 = 0.0f;
     bool round_full = false, term = false;
     int cur = kItemEmpty;
     int mode = kFetch;
@@ -469,19 +471,23 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                     if (!pair_stores(out)) {
                         out.hit_ids[at] = id;
                         if (out.hit_T) out.hit_T[at] = T;
-                    } else if (nh & 1) {  // the second of a pair: both in one 8-byte store each
-                        // streaming stores: the lists are read by the backward,
-                        // not by this launch, so they need no room in L2
-                        __builtin_nontemporal_store(
-                            (static_cast<long long>(static_cast<uint32_t>(id)) << 32) | static_cast<uint32_t>(pend_id),
-                            reinterpret_cast<long long*>(out.hit_ids + at - 1));
-                        if (out.hit_T)
-                            __builtin_nontemporal_store(
-                                (static_cast<long long>(__float_as_uint(T)) << 32) | __float_as_uint(pend_T),
-                                reinterpret_cast<long long*>(out.hit_T + at - 1));
+                    } else if ((nh & 3) == 3) {  // the fourth of a quad: all four in one store each
+                        typedef int v4i __attribute__((ext_vector_type(4)));
+                        typedef float v4f __attribute__((ext_vector_type(4)));
+                        v4i vi; vi.x = pend_id; vi.y = pend_id1; vi.z = pend_id2; vi.w = id;
+                        __builtin_nontemporal_store(vi, reinterpret_cast<v4i*>(out.hit_ids + at - 3));
+                        if (out.hit_T) {
+                            v4f vt; vt.x = pend_T; vt.y = pend_T1; vt.z = pend_T2; vt.w = T;
+                            __builtin_nontemporal_store(vt, reinterpret_cast<v4f*>(out.hit_T + at - 3));
+                        }
                     } else {
-                        pend_id = id;
-                        pend_T = T;
+                        const int c = nh & 3;
+                        pend_id = c == 0 ? id : pend_id;
+                        pend_T = c == 0 ? T : pend_T;
+                        pend_id1 = c == 1 ? id : pend_id1;
+                        pend_T1 = c == 1 ? T : pend_T1;
+                        pend_id2 = c == 2 ? id : pend_id2;
+                        pend_T2 = c == 2 ? T : pend_T2;
                     }
                 }
                 T = T * (1.0f - a);
@@ -489,9 +495,19 @@ __device__ __forceinline__ void trace_flat(const Source& src, unsigned long long
                 if (T < P.T_min) term = true;
             } else if (term || !round_full) {
                 const OutPtrs& out = src.out(lr);
-                if (out.hit_ids && pair_stores(out) && (nh & 1) && nh - 1 < out.H_cap) {  // unpaired last entry
-                    out.hit_ids[lr.r * out.H_cap + nh - 1] = pend_id;
-                    if (out.hit_T) out.hit_T[lr.r * out.H_cap + nh - 1] = pend_T;
+                const int c = nh & 3;
+                if (out.hit_ids && pair_stores(out) && c != 0 && nh - 1 < out.H_cap) {  // the last entries
+                    const int64_t b = lr.r * out.H_cap + (nh - c);
+                    out.hit_ids[b] = pend_id;
+                    if (out.hit_T) out.hit_T[b] = pend_T;
+                    if (c > 1) {
+                        out.hit_ids[b + 1] = pend_id1;
+                        if (out.hit_T) out.hit_T[b + 1] = pend_T1;
+                    }
+                    if (c > 2) {
+                        out.hit_ids[b + 2] = pend_id2;
+                        if (out.hit_T) out.hit_T[b + 2] = pend_T2;
+                    }
                 }
                 write_result<FM, CM, CT>(src, lr, O, D, T, acc, nh, ct);
                 mode = kFetch;
